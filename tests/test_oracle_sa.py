@@ -1,0 +1,140 @@
+"""Pins of the oracle's annealing loop (Sec. 2.1-2.2, Eq. (2)): special
+temperatures with closed-form outcomes, an independent re-simulation on tiny
+instances, the tracked-cost invariant, resumption and the brute-force bound."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1208_2675_amd import workloads as W
+
+
+def _pairs(n):
+    return [(r, s) for r in range(n) for s in range(r + 1, n)]
+
+
+def _fnv(h, t, r, s, d):
+    for v, nb in ((t, 8), (r & 0xFFFFFFFF, 4), (s & 0xFFFFFFFF, 4), (d & 0xFFFFFFFFFFFFFFFF, 8)):
+        for b in range(nb):
+            h ^= (v >> (8 * b)) & 0xFF
+            h = (h * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def _inst(n, seed, sym=False):
+    rng = np.random.default_rng(seed)
+    A = rng.integers(-3, 12, (n, n)).astype(np.int32)
+    B = rng.integers(-3, 12, (n, n)).astype(np.int32)
+    if sym:
+        A = np.triu(A, 1); A = (A + A.T).astype(np.int32)
+        B = np.triu(B, 1); B = (B + B.T).astype(np.int32)
+    return A, B, rng.permutation(n).astype(np.int32)
+
+
+def test_infinite_temperature_accepts_every_proposal(orc):
+    n, iters = 6, 137
+    A, B, p0 = _inst(n, 1)
+    res = orc.sa_run(A, B, p0, iters, math.inf, 1.0, seed=5, acc_cap=iters)
+    # closed form: p after t proposals is p0 composed with the first t row-major transpositions
+    p = p0.copy()
+    pairs = _pairs(n)
+    h = orc.FNV_OFFSET
+    for t in range(iters):
+        r, s = pairs[t % len(pairs)]
+        d = orc.swap_cost_by_definition(A, B, p, r, s)
+        assert tuple(res["accept_log"][t]) == (t, r, s, d)
+        h = _fnv(h, t, r, s, d)
+        p[[r, s]] = p[[s, r]]
+    assert res["accepts"] == iters
+    assert np.array_equal(res["p"], p)
+    assert res["hash"] == h
+    assert res["cost"] == orc.cost(A, B, p)
+
+
+def test_zero_temperature_is_first_improvement_descent(orc):
+    n, iters = 7, 600
+    A, B, p0 = _inst(n, 2)
+    res = orc.sa_run(A, B, p0, iters, 1e-300, 1.0, seed=5, acc_cap=iters)
+    p = p0.copy()
+    pairs = _pairs(n)
+    log = []
+    for t in range(iters):
+        r, s = pairs[t % len(pairs)]
+        d = orc.swap_cost_by_definition(A, B, p, r, s)
+        if d <= 0:
+            log.append((t, r, s, d))
+            p[[r, s]] = p[[s, r]]
+    assert [tuple(x) for x in res["accept_log"]] == log
+    assert np.array_equal(res["p"], p)
+    # after a sweep without improving swaps every swap cost is >= 0: a local minimum
+    if all(x[3] == 0 for x in log[-len(pairs):]) or (log and log[-1][0] < iters - len(pairs)):
+        assert np.all(orc.delta_matrix(A, B, res["p"]) >= 0)
+
+
+@pytest.mark.parametrize("n,sym,seed", [(2, False, 3), (5, True, 4), (7, False, 5), (9, False, 6)])
+def test_independent_resimulation(orc, n, sym, seed):
+    """A separate Python loop over the same definitions (Eq. (1) via the pinned
+    cost, math.log, the pinned generator and schedule) gives the same run."""
+    iters = 3000
+    A, B, p0 = _inst(n, seed, sym)
+    sched = orc.schedule(A, B, p0, iters)
+    T0, alpha = sched["T0"], sched["alpha"]
+    res = orc.sa_run(A, B, p0, iters, T0, alpha, seed=77, chain=3, acc_cap=iters)
+    temps = orc.temperatures(T0, alpha, iters, range(iters))
+    p = p0.copy()
+    pairs = _pairs(n)
+    log = []
+    c = orc.cost(A, B, p)
+    for t in range(iters):
+        r, s = pairs[t % len(pairs)]
+        d = orc.cost(A, B, np.where(np.arange(n) == r, p[s], np.where(np.arange(n) == s, p[r], p))) - c
+        acc = d <= 0 or (d / temps[t] + math.log(orc.uniform(77, 3, t))) < 0
+        if acc:
+            log.append((t, r, s, d))
+            p[[r, s]] = p[[s, r]]
+            c += d
+    assert [tuple(x) for x in res["accept_log"]] == log
+    assert np.array_equal(res["p"], p)
+    assert res["cost"] == c == orc.cost(A, B, p)
+    assert 0 < res["accepts"] < iters
+
+
+def test_resume_is_seamless(orc):
+    ch = W.single_chain("n32_sym", iters=200_000)
+    s = orc.schedule(ch.A, ch.B, ch.p0, ch.iters)
+    full = orc.sa_run(ch.A, ch.B, ch.p0, ch.iters, s["T0"], s["alpha"], ch.philox_seed)
+    half = orc.sa_run(ch.A, ch.B, ch.p0, ch.iters, s["T0"], s["alpha"], ch.philox_seed, t_end=77_777)
+    rest = orc.sa_run(ch.A, ch.B, half["p"], ch.iters, s["T0"], s["alpha"], ch.philox_seed,
+                      state=half["state"])
+    for k in ("accepts", "hash", "cost", "best_cost", "best_iter", "t"):
+        assert rest[k] == full[k], k
+    assert np.array_equal(rest["p"], full["p"])
+
+
+def test_config_n32_cost_invariant(orc):
+    ch = W.single_chain("n32_sym")
+    s = orc.schedule(ch.A, ch.B, ch.p0, ch.iters)
+    res = orc.sa_run(ch.A, ch.B, ch.p0, ch.iters, s["T0"], s["alpha"], ch.philox_seed)
+    assert res["cost"] == orc.cost(ch.A, ch.B, res["p"])
+    assert res["best_cost"] <= res["cost"]
+    assert sorted(res["p"].tolist()) == list(range(32))
+    assert 0 < res["accepts"] < ch.iters
+
+
+def test_annealing_never_beats_brute_force(orc):
+    for seed in range(4):
+        A, B, p0 = _inst(8, 40 + seed)
+        best, _, _ = orc.brute_force(A, B)
+        s = orc.schedule(A, B, p0, 20000)
+        res = orc.sa_run(A, B, p0, 20000, s["T0"], s["alpha"], seed=seed)
+        assert res["best_cost"] >= best and res["cost"] >= best
+
+
+def test_invalid_inputs(orc):
+    A, B, p0 = _inst(5, 9)
+    with pytest.raises(ValueError):
+        orc.sa_run(A, B, np.array([0, 0, 1, 2, 3], dtype=np.int32), 10, 1.0, 1.0, seed=0)
+    with pytest.raises(ValueError):
+        orc.sa_run(A, B, p0, 10, 0.0, 1.0, seed=0)
+    with pytest.raises(ValueError):
+        orc.sa_run(A, B, p0, 10, 1.0, 1.5, seed=0)
