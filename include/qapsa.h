@@ -1,0 +1,190 @@
+/*
+ * qapsa.h -- C ABI of libqapsa: Delta-matrix simulated annealing for the
+ * quadratic assignment problem (QAP) on AMD Instinct MI355X (gfx950).
+ *
+ * Method: G. Paul, "A GPU implementation of the Simulated Annealing Heuristic
+ * for the Quadratic Assignment Problem", arXiv 1208.2675.
+ *   - Problem, Sec. 1, Eq. (1): N facilities are placed at N locations.
+ *     A[i*N+j] is the flow between facilities i and j, B[k*N+l] the distance
+ *     between locations k and l, and p[i] the location of facility i.  The cost
+ *     of p is C(p) = sum_i sum_j A[i][j] * B[p[i]][p[j]].
+ *   - Move, Sec. 2.1: swap the locations of two facilities r and s.  Its cost
+ *     change is Delta(r,s) = C(p o (r s)) - C(p).
+ *   - Acceptance, Sec. 2.1, Eq. (2): a proposed swap is made when Delta < 0 or
+ *     exp(-Delta/T) > r, r uniform in (0, 1), T lowered after every iteration.
+ *   - Delta-matrix approach, Sec. 2.2, steps (a)-(e): keep Delta(r,s) for all
+ *     pairs; step through proposals; on an accepted swap update p and Delta.
+ *   - B' matrix, Sec. 3, Eq. (3): B'[i][j] = B[p[i]][p[j]] is kept alongside p
+ *     so that every term of an update reads A and B' at the same index.
+ *
+ * Readings fixed by this library where the paper leaves a choice open:
+ *   - Proposals enumerate the pairs r < s in row-major order, cyclically;
+ *     iteration t (0-based) proposes pair number t mod N(N-1)/2.  Every
+ *     proposal is one iteration, accepted or not.
+ *   - Delta is stored packed: the N(N-1)/2 pairs r < s in row-major order,
+ *     which is also the proposal order.  Entries are int32; every cost is int64.
+ *   - r_t of iteration t of a chain is (2u + 1) * 2^-53, where u is the 52-bit
+ *     number (x0 << 20) | (x1 >> 12) and (x0, x1, x2, x3) is Philox-4x32-10
+ *     (Salmon et al., SC'11) at counter (lo32 t, hi32 t, chain_id, 0) and key
+ *     (lo32 seed, hi32 seed).
+ *   - Eq. (2) in binary64: Delta <= 0 is accepted; otherwise with
+ *     z = fl(fl(Delta / T_t) + fl(log r_t)) the swap is made iff z < 0.
+ *     Evaluations with |z| < 1e-12 are reported as near ties.
+ *   - Cooling: geometric, T_t = ((T0 * H[t >> 20]) * M[(t >> 10) & 1023]) * L[t & 1023]
+ *     with L[0] = M[0] = H[0] = 1, L[j] = L[j-1] * alpha,
+ *     M[j] = M[j-1] * (L[1023] * alpha), H[j] = H[j-1] * (M[1023] * L[1023] * alpha).
+ *
+ * Conventions for every call:
+ *   - Pointers are DEVICE pointers unless the comment says host.  The caller
+ *     owns all memory; the library allocates none.  Matrices are row-major.
+ *   - Calls are asynchronous on `stream` and never synchronise it.  Errors in
+ *     the arguments are returned at once as a negative qap_status.  Errors
+ *     that only the device can see are written to a device status field
+ *     (qap_instance_info.status, qap_chain_state.status).
+ *   - Calls that share device buffers must be ordered by the caller (same
+ *     stream or events); calls on disjoint buffers may run concurrently.
+ */
+#ifndef QAPSA_H
+#define QAPSA_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QAP_API __attribute__((visibility("default")))
+
+typedef enum {
+    QAP_OK = 0,
+    QAP_E_INVAL = -1,        /* bad argument (null pointer, n < 2, bad schedule, ...) */
+    QAP_E_NOT_PERM = -2,     /* p is not a permutation of 0..n-1                      */
+    QAP_E_RANGE = -3,        /* the instance's values overflow the int32 Delta bound  */
+    QAP_E_NOMEM = -4,        /* a size exceeds what the chosen kernel can hold         */
+    QAP_E_DEVICE = -5,       /* a HIP runtime call failed                              */
+    QAP_E_UNSUPPORTED = -6,  /* no kernel in this build handles the request            */
+    QAP_E_STATE = -7         /* a chain state that is not ready (see qap_chain_state)  */
+} qap_status;
+
+/* Facts about an instance and start permutation, written by qap_delta_init. */
+typedef struct {
+    int64_t cost;           /* Eq. (1) at p                                         */
+    int64_t sum_abs_delta;  /* sum over r < s of |Delta(r,s)|; T0 = this / (n(n-1)/2) */
+    int32_t a_min, a_max;   /* value range of A                                     */
+    int32_t b_min, b_max;   /* value range of B                                     */
+    int32_t symmetric;      /* 1 if A == A^T and B == B^T                           */
+    int32_t status;         /* QAP_OK, QAP_E_NOT_PERM or QAP_E_RANGE                */
+} qap_instance_info;
+
+/* Device-resident state of one annealing chain; carried between calls. */
+typedef struct {
+    uint64_t t;          /* next iteration index                                      */
+    uint64_t accepts;    /* swaps made so far                                         */
+    uint64_t near_ties;  /* Eq. (2) evaluations with |z| < 1e-12 so far                */
+    uint64_t hash;       /* FNV-1a-64 over each accepted (t u64, r i32, s i32, Delta i64),
+                            little-endian, starting from 0xcbf29ce484222325            */
+    int64_t cost;        /* Eq. (1) at the current p, tracked incrementally           */
+    int64_t best_cost;   /* lowest cost reached so far                                */
+    uint64_t best_iter;  /* iterations completed when best_cost was first reached     */
+    int32_t status;      /* QAP_OK, or the first error the device saw                 */
+    int32_t reserved;
+} qap_chain_state;
+
+/* One near tie of Eq. (2). */
+typedef struct {
+    uint64_t t;
+    int64_t delta;
+    double z;            /* fl(fl(delta / T_t) + fl(log r_t)) */
+} qap_near_tie;
+
+/* Schedule of one run (host struct). */
+typedef struct {
+    uint64_t iters;      /* I, the length of the whole schedule (Sec. 2.2 step (e))    */
+    uint64_t t_end;      /* this call runs iterations state.t .. t_end-1; t_end <= iters */
+    double T0;           /* start temperature; +inf accepts every proposal            */
+    double alpha;        /* per-iteration cooling factor, 0 < alpha <= 1              */
+    uint64_t seed;       /* generator key                                             */
+    uint32_t chain_id;   /* third generator counter word                              */
+    uint32_t flags;      /* reserved, must be 0                                       */
+} qap_schedule;
+
+/* Device buffers a run reads or appends to (host struct of device pointers). */
+typedef struct {
+    const double* temps;     /* qap_temp_table_len(iters) doubles from qap_schedule_tables */
+    qap_near_tie* ties;      /* optional: first tie_cap near ties, in no fixed order       */
+    uint32_t tie_cap;
+    uint32_t reserved;
+    int64_t* accept_log;     /* optional: 4 int64 (t, r, s, Delta) per accepted swap,
+                                entry k for the k-th swap of the chain (k < accept_cap)    */
+    uint64_t accept_cap;
+} qap_run_buffers;
+
+/* Text for a qap_status value (static storage). */
+QAP_API const char* qap_strerror(int status);
+
+/*
+ * Eq. (1): *cost = sum_ij A[i][j] * B[p[i]][p[j]] in int64.
+ * A, B: n*n int32; p: n int32, a permutation (entries outside 0..n-1 are
+ * counted as 0 and make *cost meaningless); cost: 1 int64.
+ */
+QAP_API int qap_cost(int32_t n, const int32_t* A, const int32_t* B, const int32_t* p,
+                     int64_t* cost, hipStream_t stream);
+
+/*
+ * Step (a) of Sec. 2.2 with Eq. (3): for permutation p build
+ *   Bp[i*n+j] = B[p[i]][p[j]]                              (n*n int32, written)
+ *   delta[idx(r,s)] = C(p o (r s)) - C(p) for all r < s     (n(n-1)/2 int32, written)
+ * and fill *info (device).  If state != NULL it is reset to a fresh chain at
+ * t = 0 with cost = info->cost.
+ * The whole Delta matrix is computed from Eq. (1) differenced over the terms
+ * that meet {r, s}, in int64, and stored as int32.  info->status becomes
+ * QAP_E_NOT_PERM if p is not a permutation and QAP_E_RANGE unless
+ *   (2n + 8) * (a_max - a_min) * (b_max - b_min) < 2^31   and
+ *   n^2 * max|A| * max|B| < 2^62;
+ * in both cases Bp and delta are left unspecified.  O(n^3) work.
+ */
+QAP_API int qap_delta_init(int32_t n, const int32_t* A, const int32_t* B, const int32_t* p,
+                           int32_t* Bp, int32_t* delta, qap_instance_info* info,
+                           qap_chain_state* state, hipStream_t stream);
+
+/* Number of doubles in the temperature table of a schedule of `iters` iterations:
+   2048 + ceil(iters / 2^20) (at least one H entry). */
+QAP_API uint64_t qap_temp_table_len(uint64_t iters);
+
+/*
+ * Fill temps (device, qap_temp_table_len(iters) doubles) with the cooling
+ * tables L (1024), M (1024) and H of a geometric schedule with factor alpha
+ * (see the reading above).  The cooling schedule of Sec. 2.1 is left open by
+ * the paper; this is the geometric one, evaluable for any t in O(1).
+ */
+QAP_API int qap_schedule_tables(uint64_t iters, double alpha, double* temps, hipStream_t stream);
+
+/*
+ * Steps (b)-(e) of Sec. 2.2 for one chain: iterations state->t .. sched->t_end-1.
+ *   A      n*n int32 flows (read)
+ *   Bp     n*n int32 B' for the current p (read, updated per accepted swap, Eq. (3))
+ *   p      n int32 permutation (read, updated)
+ *   delta  n(n-1)/2 int32 packed Delta for the current p (read, updated)
+ *   state  chain state (read, updated); state->status must be QAP_OK
+ *   sched  host: schedule (T0, alpha, iters, t_end, seed, chain_id)
+ *   info   host: the qap_instance_info qap_delta_init wrote for this instance
+ *          (copied back by the caller); selects the kernel and the value width
+ *   bufs   host struct of device pointers: temperature table (required), logs
+ * Each accepted swap (u, v) updates p and B', adds Delta(u,v) to the cost and
+ * updates every Delta entry: pairs disjoint from {u, v} by an O(1) correction,
+ * pairs that meet {u, v} by an O(n) recomputation (the general asymmetric form).
+ * The run is identical whatever the split of [0, iters) into calls.
+ * Returns QAP_E_UNSUPPORTED when no kernel of this build handles n and the
+ * value ranges, QAP_E_RANGE when info->status says so.
+ */
+QAP_API int qap_sa_run(int32_t n, const int32_t* A, int32_t* Bp, int32_t* p, int32_t* delta,
+                       qap_chain_state* state, const qap_schedule* sched,
+                       const qap_instance_info* info, const qap_run_buffers* bufs,
+                       hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QAPSA_H */

@@ -1,0 +1,53 @@
+// qapsa_internal.hpp -- declarations shared by the translation units of libqapsa.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qapsa.h"
+
+namespace qapsa {
+
+inline uint64_t temp_table_len(uint64_t iters)
+{
+    uint64_t nh = (iters + (1ull << 20) - 1) >> 20;
+    return 2048 + (nh ? nh : 1);
+}
+
+// Everything one chain's kernel needs; passed by value.
+struct ChainArgs {
+    int32_t n;
+    int32_t pitch;        // LDS row pitch of A and B' (int16 elements, odd)
+    int32_t max_step;     // most proposals per lane in one scan step
+    int32_t flags;
+    const int32_t* A;
+    int32_t* Bp;
+    int32_t* p;
+    int32_t* delta;
+    qap_chain_state* state;
+    const double* temps;
+    qap_near_tie* ties;
+    int64_t* acc_log;
+    uint64_t acc_cap;
+    uint64_t t_end;
+    double T0;
+    uint64_t seed;
+    uint32_t chain_id;
+    uint32_t tie_cap;
+};
+
+// LDS footprint (bytes) of the one-workgroup chain kernel.
+size_t lds_chain_bytes(int n, bool symmetric, bool a_in_lds);
+constexpr size_t kLdsLimit = 160 * 1024;
+constexpr size_t kLdsStaticReserve = 512;   // the kernel's static __shared__ scalars
+
+int launch_cost(int n, const int32_t* A, const int32_t* B, const int32_t* p, int64_t* cost,
+                hipStream_t stream);
+int launch_delta_init(int n, const int32_t* A, const int32_t* B, const int32_t* p, int32_t* Bp,
+                      int32_t* delta, qap_instance_info* info, qap_chain_state* state,
+                      hipStream_t stream);
+int launch_schedule_tables(uint64_t iters, double alpha, double* temps, hipStream_t stream);
+int launch_chain_lds(const ChainArgs& a, bool symmetric, bool a_in_lds, int threads,
+                     hipStream_t stream);
+
+}  // namespace qapsa

@@ -1,0 +1,230 @@
+"""Python binding of libqapsa (ctypes).
+
+The functions named ``qap_*`` mirror the C ABI in ``include/qapsa.h`` one to
+one and only marshal arguments: device buffers are torch tensors on a ROCm
+device (or raw integer addresses), streams are ``torch.cuda.Stream`` objects
+(or raw handles).  Every step of the annealing runs in the HIP kernels.
+
+``Chain`` is a convenience holder for one chain's device buffers that calls
+those functions in the order the method needs (set-up, schedule, run).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqapsa.so")
+
+QAP_OK, QAP_E_INVAL, QAP_E_NOT_PERM, QAP_E_RANGE = 0, -1, -2, -3
+QAP_E_NOMEM, QAP_E_DEVICE, QAP_E_UNSUPPORTED, QAP_E_STATE = -4, -5, -6, -7
+
+
+class QapError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {qap_strerror(status)} ({status})")
+        self.status = status
+
+
+class InstanceInfo(C.Structure):
+    _fields_ = [("cost", C.c_int64), ("sum_abs_delta", C.c_int64),
+                ("a_min", C.c_int32), ("a_max", C.c_int32), ("b_min", C.c_int32), ("b_max", C.c_int32),
+                ("symmetric", C.c_int32), ("status", C.c_int32)]
+
+
+class ChainState(C.Structure):
+    _fields_ = [("t", C.c_uint64), ("accepts", C.c_uint64), ("near_ties", C.c_uint64),
+                ("hash", C.c_uint64), ("cost", C.c_int64), ("best_cost", C.c_int64),
+                ("best_iter", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32)]
+
+
+class NearTie(C.Structure):
+    _fields_ = [("t", C.c_uint64), ("delta", C.c_int64), ("z", C.c_double)]
+
+
+class Schedule(C.Structure):
+    _fields_ = [("iters", C.c_uint64), ("t_end", C.c_uint64), ("T0", C.c_double), ("alpha", C.c_double),
+                ("seed", C.c_uint64), ("chain_id", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class RunBuffers(C.Structure):
+    _fields_ = [("temps", C.c_void_p), ("ties", C.c_void_p), ("tie_cap", C.c_uint32),
+                ("reserved", C.c_uint32), ("accept_log", C.c_void_p), ("accept_cap", C.c_uint64)]
+
+
+STATE_BYTES = C.sizeof(ChainState)
+INFO_BYTES = C.sizeof(InstanceInfo)
+TIE_BYTES = C.sizeof(NearTie)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1208_2675_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, u64, i64 = C.c_void_p, C.c_int32, C.c_uint64, C.c_int64
+    L.qap_strerror.argtypes = [C.c_int]
+    L.qap_strerror.restype = C.c_char_p
+    L.qap_cost.argtypes = [i32, vp, vp, vp, vp, vp]
+    L.qap_cost.restype = C.c_int
+    L.qap_delta_init.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.qap_delta_init.restype = C.c_int
+    L.qap_temp_table_len.argtypes = [u64]
+    L.qap_temp_table_len.restype = u64
+    L.qap_schedule_tables.argtypes = [u64, C.c_double, vp, vp]
+    L.qap_schedule_tables.restype = C.c_int
+    L.qap_sa_run.argtypes = [i32, vp, vp, vp, vp, vp, C.POINTER(Schedule), C.POINTER(InstanceInfo),
+                             C.POINTER(RunBuffers), vp]
+    L.qap_sa_run.restype = C.c_int
+    return L
+
+
+_lib = _load()
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _check(rc: int, where: str):
+    if rc != QAP_OK:
+        raise QapError(rc, where)
+
+
+# ----------------------------------------------------------- the C ABI, 1:1
+
+def qap_strerror(status: int) -> str:
+    return _lib.qap_strerror(status).decode()
+
+
+def qap_cost(n, A, B, p, cost, stream=None) -> int:
+    return _lib.qap_cost(n, _ptr(A), _ptr(B), _ptr(p), _ptr(cost), _stream(stream))
+
+
+def qap_delta_init(n, A, B, p, Bp, delta, info, state=None, stream=None) -> int:
+    return _lib.qap_delta_init(n, _ptr(A), _ptr(B), _ptr(p), _ptr(Bp), _ptr(delta), _ptr(info),
+                               _ptr(state), _stream(stream))
+
+
+def qap_temp_table_len(iters: int) -> int:
+    return int(_lib.qap_temp_table_len(iters))
+
+
+def qap_schedule_tables(iters, alpha, temps, stream=None) -> int:
+    return _lib.qap_schedule_tables(iters, alpha, _ptr(temps), _stream(stream))
+
+
+def qap_sa_run(n, A, Bp, p, delta, state, sched: Schedule, info: InstanceInfo, bufs: RunBuffers,
+               stream=None) -> int:
+    return _lib.qap_sa_run(n, _ptr(A), _ptr(Bp), _ptr(p), _ptr(delta), _ptr(state), C.byref(sched),
+                           C.byref(info), C.byref(bufs), _stream(stream))
+
+
+# ------------------------------------------------------------- conveniences
+
+def geometric_alpha(iters: int, ratio: float = 1e-3) -> float:
+    """Per-iteration factor of a geometric schedule falling by `ratio` over `iters`."""
+    return 1.0 if iters <= 1 else math.pow(ratio, 1.0 / float(iters - 1))
+
+
+def _struct_from(t, cls):
+    buf = t.cpu().numpy().tobytes()
+    return cls.from_buffer_copy(buf)
+
+
+class Chain:
+    """Device buffers of one chain plus the calls of a full run.
+
+    A, B, p0: host arrays (numpy) copied to `device`.  After ``init()`` the
+    instance facts are on the host in ``self.info``; ``run(t_end)`` advances the
+    chain; ``result()`` copies the state, p and (optionally) Delta back.
+    """
+
+    def __init__(self, A, B, p0, iters: int, seed: int, chain_id: int = 0, ratio: float = 1e-3,
+                 T0: float | None = None, device: str = "cuda", stream=None, tie_cap: int = 64,
+                 accept_cap: int = 0):
+        import torch
+        self.torch = torch
+        A = np.ascontiguousarray(A, dtype=np.int32)
+        B = np.ascontiguousarray(B, dtype=np.int32)
+        self.n = n = int(A.shape[0])
+        self.m = n * (n - 1) // 2
+        self.iters = int(iters)
+        self.seed, self.chain_id, self.ratio, self.T0_override = int(seed), int(chain_id), ratio, T0
+        self.stream = stream
+        dev = torch.device(device)
+        self.A = torch.from_numpy(A).to(dev)
+        self.B = torch.from_numpy(B).to(dev)
+        self.p = torch.from_numpy(np.ascontiguousarray(p0, dtype=np.int32)).to(dev)
+        self.Bp = torch.empty((n, n), dtype=torch.int32, device=dev)
+        self.delta = torch.empty(max(self.m, 1), dtype=torch.int32, device=dev)
+        self.info_d = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
+        self.state_d = torch.zeros(STATE_BYTES, dtype=torch.uint8, device=dev)
+        self.temps = torch.empty(qap_temp_table_len(self.iters), dtype=torch.float64, device=dev)
+        self.tie_cap = tie_cap
+        self.ties = torch.zeros(max(tie_cap, 1) * TIE_BYTES, dtype=torch.uint8, device=dev)
+        self.accept_cap = accept_cap
+        self.accept_log = torch.zeros((max(accept_cap, 1), 4), dtype=torch.int64, device=dev)
+        self.info = None
+        self.sched = None
+
+    def init(self):
+        n = self.n
+        _check(qap_delta_init(n, self.A, self.B, self.p, self.Bp, self.delta, self.info_d, self.state_d,
+                              self.stream), "qap_delta_init")
+        self.torch.cuda.synchronize()
+        self.info = _struct_from(self.info_d, InstanceInfo)
+        if self.info.status != QAP_OK:
+            raise QapError(self.info.status, "qap_delta_init (device)")
+        T0 = self.T0_override if self.T0_override is not None else float(self.info.sum_abs_delta) / float(self.m)
+        alpha = geometric_alpha(self.iters, self.ratio)
+        self.sched = Schedule(self.iters, 0, T0, alpha, self.seed & (2**64 - 1), self.chain_id, 0)
+        _check(qap_schedule_tables(self.iters, alpha, self.temps, self.stream), "qap_schedule_tables")
+        return self
+
+    def buffers(self) -> RunBuffers:
+        return RunBuffers(self.temps.data_ptr(), self.ties.data_ptr(), self.tie_cap, 0,
+                          self.accept_log.data_ptr() if self.accept_cap else None, self.accept_cap)
+
+    def run(self, t_end: int | None = None):
+        self.sched.t_end = self.iters if t_end is None else int(t_end)
+        _check(qap_sa_run(self.n, self.A, self.Bp, self.p, self.delta, self.state_d, self.sched, self.info,
+                          self.buffers(), self.stream), "qap_sa_run")
+        return self
+
+    def state(self) -> ChainState:
+        self.torch.cuda.synchronize()
+        return _struct_from(self.state_d, ChainState)
+
+    def result(self, with_delta: bool = False) -> dict:
+        st = self.state()
+        if st.status != QAP_OK:
+            raise QapError(st.status, "qap_sa_run (device)")
+        out = {k: int(getattr(st, k)) for k, _ in ChainState._fields_ if k != "reserved"}
+        out["p"] = self.p.cpu().numpy()
+        nt = min(st.near_ties, self.tie_cap)
+        ties = np.frombuffer(self.ties.cpu().numpy().tobytes(), dtype=np.dtype(
+            [("t", "<u8"), ("delta", "<i8"), ("z", "<f8")]))[:nt]
+        out["near_tie_t"] = np.sort(ties["t"])
+        out["T0"], out["alpha"] = self.sched.T0, self.sched.alpha
+        if with_delta:
+            out["delta"] = self.delta.cpu().numpy().astype(np.int64)[: self.m]
+            out["Bp"] = self.Bp.cpu().numpy()
+        if self.accept_cap:
+            out["accept_log"] = self.accept_log.cpu().numpy()[: min(st.accepts, self.accept_cap)]
+        return out

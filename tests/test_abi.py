@@ -1,0 +1,84 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, its structs have the layout the binding assumes, and argument
+errors are reported before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qapsa.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return re.findall(r"QAP_API\s+[\w\s\*]+?\b(qap_\w+)\s*\(", text)
+
+
+@pytest.fixture(scope="module")
+def qlib():
+    path = os.path.join(ROOT, "paper_1208_2675_amd", "libqapsa.so")
+    if not os.path.exists(path):
+        from paper_1208_2675_amd import build
+        build.build()
+    return C.CDLL(path)
+
+
+def test_header_declares_the_boundary():
+    names = set(_declared())
+    assert {"qap_strerror", "qap_cost", "qap_delta_init", "qap_temp_table_len",
+            "qap_schedule_tables", "qap_sa_run"} <= names
+
+
+def test_every_declared_symbol_is_exported(qlib):
+    for name in _declared():
+        assert hasattr(qlib, name), name
+
+
+def test_struct_layout_matches_binding(tmp_path):
+    from paper_1208_2675_amd import qapsa as Q
+    src = tmp_path / "sz.c"
+    src.write_text('#include "qapsa.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\","
+                   "sizeof(qap_instance_info), sizeof(qap_chain_state), sizeof(qap_near_tie),"
+                   "sizeof(qap_schedule), sizeof(qap_run_buffers), offsetof(qap_chain_state, status),"
+                   "offsetof(qap_run_buffers, accept_log));return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                    "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [C.sizeof(Q.InstanceInfo), C.sizeof(Q.ChainState), C.sizeof(Q.NearTie),
+                   C.sizeof(Q.Schedule), C.sizeof(Q.RunBuffers), Q.ChainState.status.offset,
+                   Q.RunBuffers.accept_log.offset]
+
+
+def test_host_side_argument_errors(qlib):
+    """These calls must fail in argument checking, before touching any device."""
+    from paper_1208_2675_amd import qapsa as Q
+    assert Q.qap_strerror(Q.QAP_E_RANGE).startswith("instance values")
+    assert Q.qap_temp_table_len(10**9) == 2048 + 954
+    assert Q.qap_temp_table_len(1) == 2049
+    fake = 0x1000  # never dereferenced: every call below is rejected first
+    info = Q.InstanceInfo(0, 0, 0, 9, 0, 9, 1, 0)
+    bufs = Q.RunBuffers(fake, None, 0, 0, None, 0)
+    ok = Q.Schedule(100, 100, 1.0, 0.99, 1, 0, 0)
+    assert Q.qap_sa_run(1, fake, fake, fake, fake, fake, ok, info, bufs, 0) == Q.QAP_E_INVAL
+    for bad in (Q.Schedule(100, 101, 1.0, 0.99, 1, 0, 0), Q.Schedule(100, 100, 0.0, 0.99, 1, 0, 0),
+                Q.Schedule(100, 100, float("nan"), 0.99, 1, 0, 0), Q.Schedule(100, 100, 1.0, 1.5, 1, 0, 0),
+                Q.Schedule(0, 0, 1.0, 0.5, 1, 0, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 7)):
+        assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, bad, info, bufs, 0) == Q.QAP_E_INVAL
+    assert Q.qap_sa_run(8, fake, None, fake, fake, fake, ok, info, bufs, 0) == Q.QAP_E_INVAL
+    assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, ok, info, Q.RunBuffers(None, None, 0, 0, None, 0),
+                        0) == Q.QAP_E_INVAL
+    # a device-reported error in the instance facts is passed through
+    bad_info = Q.InstanceInfo(0, 0, 0, 9, 0, 9, 1, Q.QAP_E_RANGE)
+    assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, ok, bad_info, bufs, 0) == Q.QAP_E_RANGE
+    # values outside the 16-bit working range have no kernel in this build
+    wide = Q.InstanceInfo(0, 0, 0, 70000, 0, 9, 1, 0)
+    assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, ok, wide, bufs, 0) == Q.QAP_E_UNSUPPORTED
+    assert Q.qap_cost(0, fake, fake, fake, fake, 0) == Q.QAP_E_INVAL
+    assert Q.qap_delta_init(1, fake, fake, fake, fake, fake, fake, None, 0) == Q.QAP_E_INVAL
+    assert Q.qap_schedule_tables(0, 0.5, fake, 0) == Q.QAP_E_INVAL
+    assert Q.qap_schedule_tables(10, 1.5, fake, 0) == Q.QAP_E_INVAL
