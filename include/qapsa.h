@@ -82,14 +82,21 @@ typedef struct {
     uint64_t t;          /* next iteration index                                      */
     uint64_t accepts;    /* swaps made so far                                         */
     uint64_t near_ties;  /* Eq. (2) evaluations with |z| < 1e-12 so far                */
-    uint64_t hash;       /* FNV-1a-64 over each accepted (t u64, r i32, s i32, Delta i64),
-                            little-endian, starting from 0xcbf29ce484222325            */
+    uint64_t hash;       /* sum mod 2^64 over accepted swaps (t, r, s, Delta) of
+                            f(f(f(t) ^ (r << 32 | s)) ^ Delta), f the splitmix64 output
+                            function; starts at 0                                      */
     int64_t cost;        /* Eq. (1) at the current p, tracked incrementally           */
     int64_t best_cost;   /* lowest cost reached so far                                */
     uint64_t best_iter;  /* iterations completed when best_cost was first reached     */
     int32_t status;      /* QAP_OK, or the first error the device saw                 */
-    int32_t reserved;
+    int32_t mode;        /* how swap costs are produced: QAP_MODE_SCRATCH (each proposal's
+                            cost computed in O(N) when it is met) or QAP_MODE_DELTA (the
+                            Delta matrix of Sec. 2.2 is kept); the caller's delta buffer
+                            holds Delta for the current p in both modes                 */
 } qap_chain_state;
+
+#define QAP_MODE_SCRATCH 0
+#define QAP_MODE_DELTA 1
 
 /* One near tie of Eq. (2). */
 typedef struct {
@@ -106,8 +113,17 @@ typedef struct {
     double alpha;        /* per-iteration cooling factor, 0 < alpha <= 1              */
     uint64_t seed;       /* generator key                                             */
     uint32_t chain_id;   /* third generator counter word                              */
-    uint32_t flags;      /* reserved, must be 0                                       */
+    uint32_t flags;      /* 0, QAP_FLAG_DELTA_ONLY or QAP_FLAG_SCRATCH_ONLY           */
+    uint32_t switch_permille; /* a chain in scratch mode moves to Delta mode when fewer
+                            than this many proposals per 1000 were accepted over the
+                            last 8192 iterations; 0 selects the default (20)          */
+    uint32_t reserved;   /* must be 0                                                 */
 } qap_schedule;
+
+/* qap_schedule.flags.  The run is the same whichever mode produces the swap
+   costs; the flags only pin the mode. */
+#define QAP_FLAG_DELTA_ONLY 1u    /* keep the Delta matrix from the first iteration (Sec. 2.2) */
+#define QAP_FLAG_SCRATCH_ONLY 2u  /* never build the Delta matrix during the run              */
 
 /* Device buffers a run reads or appends to (host struct of device pointers). */
 typedef struct {
@@ -118,7 +134,31 @@ typedef struct {
     int64_t* accept_log;     /* optional: 4 int64 (t, r, s, Delta) per accepted swap,
                                 entry k for the k-th swap of the chain (k < accept_cap)    */
     uint64_t accept_cap;
+    uint64_t* phase_cycles;  /* optional: QAP_PHASES counters, added to (see qap_phase)   */
 } qap_run_buffers;
+
+/* Indices of qap_run_buffers.phase_cycles: shader-clock cycles spent per phase
+   and event counts, accumulated over calls.  Recorded by the first thread of
+   the workgroup that runs a chain; phases end at workgroup barriers. */
+enum {
+    QAP_PH_TOTAL = 0,          /* cycles in the iteration loop                     */
+    QAP_PH_SCRATCH_THRESH = 1, /* cycles computing acceptance thresholds          */
+    QAP_PH_SCRATCH_EVAL = 2,   /* cycles evaluating proposals from scratch        */
+    QAP_PH_SCRATCH_ACCEPT = 3, /* cycles making swaps in scratch mode             */
+    QAP_PH_DELTA_SCAN = 4,     /* cycles scanning Delta                            */
+    QAP_PH_DELTA_UPDATE = 5,   /* cycles updating Delta after swaps                */
+    QAP_PH_BUILD = 6,          /* cycles rebuilding Delta from scratch             */
+    QAP_PH_IO = 7,             /* cycles loading and writing back state            */
+    QAP_PH_N_ROUNDS = 8,       /* scratch-mode rounds                              */
+    QAP_PH_N_SCRATCH_ACC = 9,  /* swaps made in scratch mode                       */
+    QAP_PH_N_SCAN_STEPS = 10,  /* Delta-mode scan steps                            */
+    QAP_PH_N_DELTA_ACC = 11,   /* swaps made in Delta mode                         */
+    QAP_PH_N_THRESH = 12,      /* threshold refills                                */
+    QAP_PH_SWITCH_T = 13,      /* iteration at which the chain entered Delta mode  */
+    QAP_PH_N_SCANNED = 14,     /* proposals tested in Delta mode                   */
+    QAP_PH_RESERVED = 15,
+    QAP_PHASES = 16
+};
 
 /* Text for a qap_status value (static storage). */
 QAP_API const char* qap_strerror(int status);
@@ -136,7 +176,7 @@ QAP_API int qap_cost(int32_t n, const int32_t* A, const int32_t* B, const int32_
  *   Bp[i*n+j] = B[p[i]][p[j]]                              (n*n int32, written)
  *   delta[idx(r,s)] = C(p o (r s)) - C(p) for all r < s     (n(n-1)/2 int32, written)
  * and fill *info (device).  If state != NULL it is reset to a fresh chain at
- * t = 0 with cost = info->cost.
+ * t = 0 with cost = info->cost, in QAP_MODE_SCRATCH.
  * The whole Delta matrix is computed from Eq. (1) differenced over the terms
  * that meet {r, s}, in int64, and stored as int32.  info->status becomes
  * QAP_E_NOT_PERM if p is not a permutation and QAP_E_RANGE unless
@@ -171,10 +211,13 @@ QAP_API int qap_schedule_tables(uint64_t iters, double alpha, double* temps, hip
  *   info   host: the qap_instance_info qap_delta_init wrote for this instance
  *          (copied back by the caller); selects the kernel and the value width
  *   bufs   host struct of device pointers: temperature table (required), logs
- * Each accepted swap (u, v) updates p and B', adds Delta(u,v) to the cost and
- * updates every Delta entry: pairs disjoint from {u, v} by an O(1) correction,
- * pairs that meet {u, v} by an O(n) recomputation (the general asymmetric form).
- * The run is identical whatever the split of [0, iters) into calls.
+ * Each accepted swap (u, v) updates p and B' and adds Delta(u,v) to the cost.
+ * In QAP_MODE_DELTA it also updates every Delta entry: pairs disjoint from
+ * {u, v} by an O(1) correction, pairs that meet {u, v} by an O(n)
+ * recomputation (the general asymmetric form).  In QAP_MODE_SCRATCH each
+ * proposal's swap cost is computed in O(n) when it is met, and Delta is rebuilt
+ * at the end of the call.  The run is identical whatever the split of
+ * [0, iters) into calls and whichever mode is active.
  * Returns QAP_E_UNSUPPORTED when no kernel of this build handles n and the
  * value ranges, QAP_E_RANGE when info->status says so.
  */

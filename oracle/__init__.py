@@ -77,8 +77,8 @@ def lib():
         L.orc_temperature_tables.restype = None
         L.orc_temperature.argtypes = [C.c_double, f64p, f64p, f64p, C.c_uint64]
         L.orc_temperature.restype = C.c_double
-        L.orc_hash_accept.argtypes = [C.c_uint64, C.c_uint64, C.c_int32, C.c_int32, C.c_int64]
-        L.orc_hash_accept.restype = C.c_uint64
+        L.orc_accept_fingerprint.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int64]
+        L.orc_accept_fingerprint.restype = C.c_uint64
         L.orc_state_init.argtypes = [C.c_int32, i32p, i32p, i32p, C.POINTER(State)]
         L.orc_state_init.restype = None
         L.orc_sa_run.argtypes = [C.c_int32, i32p, i32p, i32p, C.POINTER(State),
@@ -91,8 +91,6 @@ def lib():
         _lib = L
     return _lib
 
-
-FNV_OFFSET = 0xCBF29CE484222325
 
 
 def _mats(A, B):
@@ -169,8 +167,8 @@ def temperatures(T0: float, alpha: float, iters: int, ts) -> np.ndarray:
     return np.array([f(T0, L, M, H, int(t)) for t in ts])
 
 
-def hash_accept(h: int, t: int, r: int, s: int, delta: int) -> int:
-    return int(lib().orc_hash_accept(h, t, r, s, delta))
+def accept_fingerprint(t: int, r: int, s: int, delta: int) -> int:
+    return int(lib().orc_accept_fingerprint(t, r, s, delta))
 
 
 def schedule(A, B, p, iters: int, ratio: float = 1e-3) -> dict:

@@ -243,30 +243,33 @@ typedef struct {
     uint64_t t;          /* next iteration index                                  */
     uint64_t accepts;    /* swaps made so far                                     */
     uint64_t near_ties;  /* Metropolis tests with |z| < 1e-12 so far              */
-    uint64_t hash;       /* FNV-1a-64 over each accepted (t, r, s, delta), LE bytes */
+    uint64_t hash;       /* sum of orc_accept_fingerprint over accepted swaps      */
     int64_t cost;        /* Eq. (1) at the current p, tracked incrementally       */
     int64_t best_cost;   /* lowest cost seen                                      */
     uint64_t best_iter;  /* iterations completed when best_cost was first reached */
 } orc_state;
 
-#define ORC_FNV_OFFSET 0xcbf29ce484222325ull
-#define ORC_FNV_PRIME 0x100000001b3ull
-
-static uint64_t orc_fnv_bytes(uint64_t h, uint64_t v, int nbytes)
+/*
+ * Trajectory hash (a checksum for comparing runs, not part of the method): the
+ * sum mod 2^64 over accepted swaps of fp(t, r, s, delta) =
+ * f(f(f(t) ^ (r << 32 | s)) ^ delta), with f the output function of splitmix64
+ * (Steele, Lea, Flood, "Fast splittable pseudorandom number generators",
+ * OOPSLA 2014).  Distinct accepted swaps have distinct t, so the sum still
+ * identifies the sequence.
+ */
+static uint64_t orc_splitmix_out(uint64_t z)
 {
-    for (int b = 0; b < nbytes; ++b) {
-        h ^= (v >> (8 * b)) & 0xffu;
-        h *= ORC_FNV_PRIME;
-    }
-    return h;
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
 }
 
-uint64_t orc_hash_accept(uint64_t h, uint64_t t, int32_t r, int32_t s, int64_t delta)
+uint64_t orc_accept_fingerprint(uint64_t t, int32_t r, int32_t s, int64_t delta)
 {
-    h = orc_fnv_bytes(h, t, 8);
-    h = orc_fnv_bytes(h, (uint32_t)r, 4);
-    h = orc_fnv_bytes(h, (uint32_t)s, 4);
-    return orc_fnv_bytes(h, (uint64_t)delta, 8);
+    uint64_t h = orc_splitmix_out(t);
+    h = orc_splitmix_out(h ^ (((uint64_t)(uint32_t)r << 32) | (uint64_t)(uint32_t)s));
+    return orc_splitmix_out(h ^ (uint64_t)delta);
 }
 
 /* Fresh chain state for permutation p: cost by Eq. (1), empty logs. */
@@ -275,7 +278,7 @@ void orc_state_init(int32_t n, const int32_t *A, const int32_t *B, const int32_t
     st->t = 0;
     st->accepts = 0;
     st->near_ties = 0;
-    st->hash = ORC_FNV_OFFSET;
+    st->hash = 0;
     st->cost = orc_cost(n, A, B, p);
     st->best_cost = st->cost;
     st->best_iter = 0;
@@ -357,7 +360,7 @@ int orc_sa_run(int32_t n, const int32_t *A, const int32_t *B, int32_t *p, orc_st
                 e[0] = (int64_t)t; e[1] = r; e[2] = s; e[3] = delta;
             }
             st->accepts++;
-            st->hash = orc_hash_accept(st->hash, t, r, s, delta);
+            st->hash += orc_accept_fingerprint(t, r, s, delta);
             if (st->cost < st->best_cost) {
                 st->best_cost = st->cost;
                 st->best_iter = t + 1;

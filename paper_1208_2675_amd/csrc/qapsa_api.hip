@@ -21,7 +21,9 @@ int check_schedule(const qap_schedule* s)
     if (s->iters == 0 || s->t_end > s->iters) return QAP_E_INVAL;
     if (!(s->T0 > 0.0)) return QAP_E_INVAL;                // rejects NaN and <= 0; +inf allowed
     if (!(s->alpha > 0.0) || s->alpha > 1.0) return QAP_E_INVAL;
-    if (s->flags != 0) return QAP_E_INVAL;
+    if ((s->flags & ~(QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY)) != 0) return QAP_E_INVAL;
+    if ((s->flags & QAP_FLAG_DELTA_ONLY) && (s->flags & QAP_FLAG_SCRATCH_ONLY)) return QAP_E_INVAL;
+    if (s->switch_permille > 1000 || s->reserved != 0) return QAP_E_INVAL;
     return QAP_OK;
 }
 
@@ -76,27 +78,40 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, int32_t* Bp, int32_t* p, int
     const int rc = check_schedule(sched);
     if (rc != QAP_OK) return rc;
     if (info->status != QAP_OK) return info->status;
-    if (!fits16(info->a_min, info->a_max) || !fits16(info->b_min, info->b_max)) return QAP_E_UNSUPPORTED;
-
     const bool sym = info->symmetric != 0;
     const size_t budget = kLdsLimit - kLdsStaticReserve;
-    bool a_lds;
-    if (lds_chain_bytes(n, sym, true) <= budget) a_lds = true;
-    else if (lds_chain_bytes(n, sym, false) <= budget) a_lds = false;
-    else return QAP_E_UNSUPPORTED;
 
     ChainArgs a{};
     a.n = n;
-    a.pitch = n | 1;
     a.max_step = 16;
+    a.flags = sched->flags;
+    a.switch_permille = sched->switch_permille ? sched->switch_permille : 20;
+    a.a_min = info->a_min;
+    a.b_min = info->b_min;
     a.A = A; a.Bp = Bp; a.p = p; a.delta = delta; a.state = state;
     a.temps = bufs->temps;
     a.ties = bufs->ties; a.tie_cap = bufs->tie_cap;
     a.acc_log = bufs->accept_log; a.acc_cap = bufs->accept_log ? bufs->accept_cap : 0;
+    a.prof = bufs->phase_cycles;
+    a.iters = sched->iters;
     a.t_end = sched->t_end;
     a.T0 = sched->T0;
     a.seed = sched->seed;
     a.chain_id = sched->chain_id;
+
+    // byte-valued kernel: value ranges of A and B fit 0..255 after shifting
+    const bool bytes_ok = (int64_t)info->a_max - info->a_min <= 255 && (int64_t)info->b_max - info->b_min <= 255;
+    if (bytes_ok && lds_wg_bytes(n, sym) <= budget) {
+        const int threads = n >= 48 ? 1024 : 256;
+        return launch_chain_wg(a, sym, threads, stream);
+    }
+    // 16-bit kernel (Delta mode only)
+    if (!fits16(info->a_min, info->a_max) || !fits16(info->b_min, info->b_max)) return QAP_E_UNSUPPORTED;
+    bool a_lds;
+    if (lds_chain_bytes(n, sym, true) <= budget) a_lds = true;
+    else if (lds_chain_bytes(n, sym, false) <= budget) a_lds = false;
+    else return QAP_E_UNSUPPORTED;
+    a.pitch = n | 1;
     const int threads = n >= 64 ? 1024 : 256;
     return launch_chain_lds(a, sym, a_lds, threads, stream);
 }

@@ -192,7 +192,7 @@ __device__ void chain_body(const ChainArgs& a, char* smem)
                 e[0] = (int64_t)tstar; e[1] = u; e[2] = v; e[3] = dstar;
             }
             s_acc += 1;
-            s_hash = hash_accept(s_hash, tstar, u, v, dstar);
+            s_hash += accept_fingerprint(tstar, u, v, dstar);
             if (s_cost < s_best) { s_best = s_cost; s_best_iter = tstar + 1; }
             swap_lds(L.Bs[u * P + u], L.Bs[v * P + v]);
             swap_lds(L.Bs[u * P + v], L.Bs[v * P + u]);
@@ -303,7 +303,7 @@ __device__ void chain_body(const ChainArgs& a, char* smem)
         qap_chain_state st;
         st.t = t; st.accepts = s_acc; st.near_ties = s_ties; st.hash = s_hash;
         st.cost = s_cost; st.best_cost = s_best; st.best_iter = s_best_iter;
-        st.status = QAP_OK; st.reserved = 0;
+        st.status = QAP_OK; st.mode = QAP_MODE_DELTA;
         *a.state = st;
     }
 }

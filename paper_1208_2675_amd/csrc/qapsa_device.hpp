@@ -78,24 +78,23 @@ __device__ __forceinline__ bool metropolis_positive(int64_t delta, double T, dou
 constexpr double kNearTie = 1e-12;
 
 // ------------------------------------------------------------------- hash
-constexpr uint64_t kFnvOffset = 0xcbf29ce484222325ull;
-constexpr uint64_t kFnvPrime = 0x100000001b3ull;
-
-__device__ __forceinline__ uint64_t fnv_bytes(uint64_t h, uint64_t v, int nbytes)
+// The trajectory hash is the sum mod 2^64 over accepted swaps of a fingerprint
+// of (t, r, s, Delta); the sum does not depend on the order in which swaps are
+// folded in, so it can be accumulated in bulk.  The fingerprint chains three
+// rounds of the splitmix64 output function (Steele, Lea, Flood, OOPSLA 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
 {
-    for (int b = 0; b < nbytes; ++b) {
-        h ^= (v >> (8 * b)) & 0xffull;
-        h *= kFnvPrime;
-    }
-    return h;
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ uint64_t hash_accept(uint64_t h, uint64_t t, int32_t r, int32_t s, int64_t d)
+__device__ __forceinline__ uint64_t accept_fingerprint(uint64_t t, int32_t r, int32_t s, int64_t d)
 {
-    h = fnv_bytes(h, t, 8);
-    h = fnv_bytes(h, (uint32_t)r, 4);
-    h = fnv_bytes(h, (uint32_t)s, 4);
-    return fnv_bytes(h, (uint64_t)d, 8);
+    uint64_t h = mix64(t);
+    h = mix64(h ^ (((uint64_t)(uint32_t)r << 32) | (uint32_t)s));
+    return mix64(h ^ (uint64_t)d);
 }
 
 // ------------------------------------------------------------ pair index

@@ -212,12 +212,12 @@ __global__ void k_state_reset(const qap_instance_info* info, qap_chain_state* st
     st->t = 0;
     st->accepts = 0;
     st->near_ties = 0;
-    st->hash = kFnvOffset;
+    st->hash = 0;
     st->cost = info->cost;
     st->best_cost = info->cost;
     st->best_iter = 0;
     st->status = info->status;
-    st->reserved = 0;
+    st->mode = QAP_MODE_SCRATCH;
 }
 
 // Cooling tables of a geometric schedule: three serial recurrences (one thread).

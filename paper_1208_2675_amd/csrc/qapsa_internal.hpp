@@ -15,11 +15,17 @@ inline uint64_t temp_table_len(uint64_t iters)
 }
 
 // Everything one chain's kernel needs; passed by value.
+constexpr uint32_t kFlagDeltaOnly = QAP_FLAG_DELTA_ONLY;
+constexpr uint32_t kFlagScratchOnly = QAP_FLAG_SCRATCH_ONLY;
+
 struct ChainArgs {
     int32_t n;
-    int32_t pitch;        // LDS row pitch of A and B' (int16 elements, odd)
+    int32_t pitch;        // LDS row pitch of A and B' (int16 elements, odd; 16-bit kernel)
+    int32_t quads;        // LDS row pitch in dwords (odd; byte kernel)
     int32_t max_step;     // most proposals per lane in one scan step
-    int32_t flags;
+    uint32_t flags;
+    uint32_t switch_permille;
+    int32_t a_min, b_min; // value shifts of the byte kernel
     const int32_t* A;
     int32_t* Bp;
     int32_t* p;
@@ -29,6 +35,8 @@ struct ChainArgs {
     qap_near_tie* ties;
     int64_t* acc_log;
     uint64_t acc_cap;
+    uint64_t* prof;       // optional phase counters (QAP_PHASES)
+    uint64_t iters;
     uint64_t t_end;
     double T0;
     uint64_t seed;
@@ -49,5 +57,10 @@ int launch_delta_init(int n, const int32_t* A, const int32_t* B, const int32_t* 
 int launch_schedule_tables(uint64_t iters, double alpha, double* temps, hipStream_t stream);
 int launch_chain_lds(const ChainArgs& a, bool symmetric, bool a_in_lds, int threads,
                      hipStream_t stream);
+
+// byte-valued chain kernel (scratch and Delta modes)
+int wg_quads(int n);
+size_t lds_wg_bytes(int n, bool symmetric);
+int launch_chain_wg(const ChainArgs& a, bool symmetric, int threads, hipStream_t stream);
 
 }  // namespace qapsa

@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libqapsa.so")
 
 QAP_OK, QAP_E_INVAL, QAP_E_NOT_PERM, QAP_E_RANGE = 0, -1, -2, -3
 QAP_E_NOMEM, QAP_E_DEVICE, QAP_E_UNSUPPORTED, QAP_E_STATE = -4, -5, -6, -7
+QAP_MODE_SCRATCH, QAP_MODE_DELTA = 0, 1
+QAP_FLAG_DELTA_ONLY, QAP_FLAG_SCRATCH_ONLY = 1, 2
 
 
 class QapError(RuntimeError):
@@ -38,7 +40,7 @@ class InstanceInfo(C.Structure):
 class ChainState(C.Structure):
     _fields_ = [("t", C.c_uint64), ("accepts", C.c_uint64), ("near_ties", C.c_uint64),
                 ("hash", C.c_uint64), ("cost", C.c_int64), ("best_cost", C.c_int64),
-                ("best_iter", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32)]
+                ("best_iter", C.c_uint64), ("status", C.c_int32), ("mode", C.c_int32)]
 
 
 class NearTie(C.Structure):
@@ -47,12 +49,19 @@ class NearTie(C.Structure):
 
 class Schedule(C.Structure):
     _fields_ = [("iters", C.c_uint64), ("t_end", C.c_uint64), ("T0", C.c_double), ("alpha", C.c_double),
-                ("seed", C.c_uint64), ("chain_id", C.c_uint32), ("flags", C.c_uint32)]
+                ("seed", C.c_uint64), ("chain_id", C.c_uint32), ("flags", C.c_uint32),
+                ("switch_permille", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class RunBuffers(C.Structure):
     _fields_ = [("temps", C.c_void_p), ("ties", C.c_void_p), ("tie_cap", C.c_uint32),
-                ("reserved", C.c_uint32), ("accept_log", C.c_void_p), ("accept_cap", C.c_uint64)]
+                ("reserved", C.c_uint32), ("accept_log", C.c_void_p), ("accept_cap", C.c_uint64),
+                ("phase_cycles", C.c_void_p)]
+
+
+PHASES = ["total", "scratch_thresh", "scratch_eval", "scratch_accept", "delta_scan", "delta_update", "build",
+          "io", "n_rounds", "n_scratch_acc", "n_scan_steps", "n_delta_acc", "n_thresh", "switch_t", "n_scanned",
+          "reserved"]
 
 
 STATE_BYTES = C.sizeof(ChainState)
@@ -157,7 +166,7 @@ class Chain:
 
     def __init__(self, A, B, p0, iters: int, seed: int, chain_id: int = 0, ratio: float = 1e-3,
                  T0: float | None = None, device: str = "cuda", stream=None, tie_cap: int = 64,
-                 accept_cap: int = 0):
+                 accept_cap: int = 0, flags: int = 0, switch_permille: int = 0, profile: bool = False):
         import torch
         self.torch = torch
         A = np.ascontiguousarray(A, dtype=np.int32)
@@ -166,6 +175,7 @@ class Chain:
         self.m = n * (n - 1) // 2
         self.iters = int(iters)
         self.seed, self.chain_id, self.ratio, self.T0_override = int(seed), int(chain_id), ratio, T0
+        self.flags, self.switch_permille = int(flags), int(switch_permille)
         self.stream = stream
         dev = torch.device(device)
         self.A = torch.from_numpy(A).to(dev)
@@ -180,6 +190,7 @@ class Chain:
         self.ties = torch.zeros(max(tie_cap, 1) * TIE_BYTES, dtype=torch.uint8, device=dev)
         self.accept_cap = accept_cap
         self.accept_log = torch.zeros((max(accept_cap, 1), 4), dtype=torch.int64, device=dev)
+        self.prof = torch.zeros(len(PHASES), dtype=torch.int64, device=dev) if profile else None
         self.info = None
         self.sched = None
 
@@ -193,13 +204,20 @@ class Chain:
             raise QapError(self.info.status, "qap_delta_init (device)")
         T0 = self.T0_override if self.T0_override is not None else float(self.info.sum_abs_delta) / float(self.m)
         alpha = geometric_alpha(self.iters, self.ratio)
-        self.sched = Schedule(self.iters, 0, T0, alpha, self.seed & (2**64 - 1), self.chain_id, 0)
+        self.sched = Schedule(self.iters, 0, T0, alpha, self.seed & (2**64 - 1), self.chain_id, self.flags,
+                              self.switch_permille, 0)
         _check(qap_schedule_tables(self.iters, alpha, self.temps, self.stream), "qap_schedule_tables")
         return self
 
     def buffers(self) -> RunBuffers:
         return RunBuffers(self.temps.data_ptr(), self.ties.data_ptr(), self.tie_cap, 0,
-                          self.accept_log.data_ptr() if self.accept_cap else None, self.accept_cap)
+                          self.accept_log.data_ptr() if self.accept_cap else None, self.accept_cap,
+                          self.prof.data_ptr() if self.prof is not None else None)
+
+    def phases(self) -> dict:
+        """Phase counters of the runs so far (cycles of the shader clock, counts)."""
+        v = self.prof.cpu().numpy().tolist()
+        return {k: int(x) for k, x in zip(PHASES, v) if k != "reserved"}
 
     def run(self, t_end: int | None = None):
         self.sched.t_end = self.iters if t_end is None else int(t_end)
@@ -215,7 +233,7 @@ class Chain:
         st = self.state()
         if st.status != QAP_OK:
             raise QapError(st.status, "qap_sa_run (device)")
-        out = {k: int(getattr(st, k)) for k, _ in ChainState._fields_ if k != "reserved"}
+        out = {k: int(getattr(st, k)) for k, _ in ChainState._fields_}
         out["p"] = self.p.cpu().numpy()
         nt = min(st.near_ties, self.tie_cap)
         ties = np.frombuffer(self.ties.cpu().numpy().tobytes(), dtype=np.dtype(

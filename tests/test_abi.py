@@ -63,11 +63,13 @@ def test_host_side_argument_errors(qlib):
     fake = 0x1000  # never dereferenced: every call below is rejected first
     info = Q.InstanceInfo(0, 0, 0, 9, 0, 9, 1, 0)
     bufs = Q.RunBuffers(fake, None, 0, 0, None, 0)
-    ok = Q.Schedule(100, 100, 1.0, 0.99, 1, 0, 0)
+    ok = Q.Schedule(100, 100, 1.0, 0.99, 1, 0, 0, 0, 0)
     assert Q.qap_sa_run(1, fake, fake, fake, fake, fake, ok, info, bufs, 0) == Q.QAP_E_INVAL
-    for bad in (Q.Schedule(100, 101, 1.0, 0.99, 1, 0, 0), Q.Schedule(100, 100, 0.0, 0.99, 1, 0, 0),
-                Q.Schedule(100, 100, float("nan"), 0.99, 1, 0, 0), Q.Schedule(100, 100, 1.0, 1.5, 1, 0, 0),
-                Q.Schedule(0, 0, 1.0, 0.5, 1, 0, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 7)):
+    for bad in (Q.Schedule(100, 101, 1.0, 0.99, 1, 0, 0, 0, 0), Q.Schedule(100, 100, 0.0, 0.99, 1, 0, 0, 0, 0),
+                Q.Schedule(100, 100, float("nan"), 0.99, 1, 0, 0, 0, 0),
+                Q.Schedule(100, 100, 1.0, 1.5, 1, 0, 0, 0, 0), Q.Schedule(0, 0, 1.0, 0.5, 1, 0, 0, 0, 0),
+                Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 7, 0, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 3, 0, 0),
+                Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 0, 1001, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 0, 0, 1)):
         assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, bad, info, bufs, 0) == Q.QAP_E_INVAL
     assert Q.qap_sa_run(8, fake, None, fake, fake, fake, ok, info, bufs, 0) == Q.QAP_E_INVAL
     assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, ok, info, Q.RunBuffers(None, None, 0, 0, None, 0),
@@ -75,7 +77,7 @@ def test_host_side_argument_errors(qlib):
     # a device-reported error in the instance facts is passed through
     bad_info = Q.InstanceInfo(0, 0, 0, 9, 0, 9, 1, Q.QAP_E_RANGE)
     assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, ok, bad_info, bufs, 0) == Q.QAP_E_RANGE
-    # values outside the 16-bit working range have no kernel in this build
+    # values outside the 16-bit working range have no single-workgroup kernel
     wide = Q.InstanceInfo(0, 0, 0, 70000, 0, 9, 1, 0)
     assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, ok, wide, bufs, 0) == Q.QAP_E_UNSUPPORTED
     assert Q.qap_cost(0, fake, fake, fake, fake, 0) == Q.QAP_E_INVAL

@@ -41,12 +41,15 @@ def _inst(n, seed, sym=False, lo=-3, hi=40):
     return A, B, rng.permutation(n).astype(np.int32)
 
 
-def _compare_run(orc, Q, A, B, p0, iters, seed, chain=0, T0=None, acc_cap=256, slices=None):
-    print(f"[case] n={A.shape[0]} iters={iters} seed={seed} chain={chain} T0={T0}", flush=True)
+def _compare_run(orc, Q, A, B, p0, iters, seed, chain=0, T0=None, acc_cap=256, slices=None, flags=0,
+                 switch_permille=0):
+    print(f"[case] n={A.shape[0]} iters={iters} seed={seed} chain={chain} T0={T0} flags={flags} "
+          f"switch={switch_permille}", flush=True)
     sched = orc.schedule(A, B, p0, iters)
     T0o = sched["T0"] if T0 is None else T0
     ref = orc.sa_run(A, B, p0, iters, T0o, sched["alpha"], seed, chain, acc_cap=acc_cap, tie_cap=256)
-    ch = Q.Chain(A, B, p0, iters, seed, chain, T0=T0, accept_cap=acc_cap, tie_cap=256).init()
+    ch = Q.Chain(A, B, p0, iters, seed, chain, T0=T0, accept_cap=acc_cap, tie_cap=256, flags=flags,
+                 switch_permille=switch_permille).init()
     assert ch.sched.T0 == T0o and ch.sched.alpha == sched["alpha"]
     for t_end in (slices or []) + [iters]:
         ch.run(t_end)
@@ -112,17 +115,30 @@ def test_delta_init_reports_bad_inputs(Q):
 
 # -------------------------------------------------------------- chain runs
 
+MODES = [(0, 0), (1, 0), (2, 0), (0, 1000), (0, 300)]   # (flags, switch_permille)
+
+
+@pytest.mark.parametrize("flags,switch", MODES)
 @pytest.mark.parametrize("n,sym,iters", [(2, False, 500), (3, True, 700), (5, False, 3000), (8, True, 5000),
                                          (13, False, 20000), (31, True, 30000), (64, False, 40000),
-                                         (97, False, 60000), (130, True, 60000)])
-def test_chain_matches_oracle_small(orc, Q, n, sym, iters):
+                                         (97, False, 60000), (130, True, 60000), (150, False, 60000),
+                                         (190, True, 50000)])
+def test_chain_matches_oracle_small(orc, Q, n, sym, iters, flags, switch):
     A, B, p0 = _inst(n, 2000 + n, sym)
-    _compare_run(orc, Q, A, B, p0, iters, seed=123 + n, chain=n % 5)
+    _compare_run(orc, Q, A, B, p0, iters, seed=123 + n, chain=n % 5, flags=flags, switch_permille=switch)
 
 
-def test_chain_infinite_temperature(orc, Q):
+@pytest.mark.parametrize("n,sym", [(9, False), (40, True), (77, False)])
+def test_chain_wide_values_16bit_kernel(orc, Q, n, sym):
+    """Value ranges above a byte take the 16-bit kernel (Delta mode throughout)."""
+    A, B, p0 = _inst(n, 3000 + n, sym, lo=-300, hi=900)
+    _compare_run(orc, Q, A, B, p0, 20000, seed=5)
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_chain_infinite_temperature(orc, Q, flags):
     A, B, p0 = _inst(40, 77)
-    got, _ = _compare_run(orc, Q, A, B, p0, 5000, seed=9, T0=math.inf, acc_cap=5000)
+    got, _ = _compare_run(orc, Q, A, B, p0, 5000, seed=9, T0=math.inf, acc_cap=5000, flags=flags)
     assert got["accepts"] == 5000
 
 
@@ -131,9 +147,10 @@ def test_chain_near_zero_temperature(orc, Q):
     _compare_run(orc, Q, A, B, p0, 20000, seed=9, T0=1e-300)
 
 
-def test_chain_slices_are_seamless(orc, Q):
+@pytest.mark.parametrize("switch", [0, 200])
+def test_chain_slices_are_seamless(orc, Q, switch):
     A, B, p0 = _inst(45, 79)
-    _compare_run(orc, Q, A, B, p0, 50000, seed=3, slices=[1, 777, 20000, 20001, 49999])
+    _compare_run(orc, Q, A, B, p0, 50000, seed=3, slices=[1, 777, 20000, 20001, 49999], switch_permille=switch)
 
 
 def test_chain_n32_full(orc, Q, golden):
