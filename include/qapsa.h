@@ -64,7 +64,8 @@ typedef enum {
     QAP_E_NOMEM = -4,        /* a size exceeds what the chosen kernel can hold         */
     QAP_E_DEVICE = -5,       /* a HIP runtime call failed                              */
     QAP_E_UNSUPPORTED = -6,  /* no kernel in this build handles the request            */
-    QAP_E_STATE = -7         /* a chain state that is not ready (see qap_chain_state)  */
+    QAP_E_STATE = -7,        /* a chain state that is not ready (see qap_chain_state)  */
+    QAP_E_TIMEOUT = -8       /* a grid barrier of a multi-workgroup run did not complete */
 } qap_status;
 
 /* Facts about an instance and start permutation, written by qap_delta_init. */
@@ -134,7 +135,11 @@ typedef struct {
     int64_t* accept_log;     /* optional: 4 int64 (t, r, s, Delta) per accepted swap,
                                 entry k for the k-th swap of the chain (k < accept_cap)    */
     uint64_t accept_cap;
-    uint64_t* phase_cycles;  /* optional: QAP_PHASES counters, added to (see qap_phase)   */
+    uint64_t* phase_cycles;  /* optional: QAP_PHASES counters, added to (see below)         */
+    void* workspace;         /* qap_workspace_bytes(n) bytes of device memory, required when
+                                the run spreads over several workgroups (large n); the
+                                library initialises it on every call                      */
+    uint64_t workspace_bytes;
 } qap_run_buffers;
 
 /* Indices of qap_run_buffers.phase_cycles: shader-clock cycles spent per phase
@@ -188,6 +193,10 @@ QAP_API int qap_delta_init(int32_t n, const int32_t* A, const int32_t* B, const 
                            int32_t* Bp, int32_t* delta, qap_instance_info* info,
                            qap_chain_state* state, hipStream_t stream);
 
+/* Bytes of device workspace a run of an n-facility instance may need
+   (qap_run_buffers.workspace); 64 + 16 n. */
+QAP_API uint64_t qap_workspace_bytes(int32_t n);
+
 /* Number of doubles in the temperature table of a schedule of `iters` iterations:
    2048 + ceil(iters / 2^20) (at least one H entry). */
 QAP_API uint64_t qap_temp_table_len(uint64_t iters);
@@ -203,6 +212,7 @@ QAP_API int qap_schedule_tables(uint64_t iters, double alpha, double* temps, hip
 /*
  * Steps (b)-(e) of Sec. 2.2 for one chain: iterations state->t .. sched->t_end-1.
  *   A      n*n int32 flows (read)
+ *   B      n*n int32 distances (read; rows of B' are regathered from B and p)
  *   Bp     n*n int32 B' for the current p (read, updated per accepted swap, Eq. (3))
  *   p      n int32 permutation (read, updated)
  *   delta  n(n-1)/2 int32 packed Delta for the current p (read, updated)
@@ -218,13 +228,71 @@ QAP_API int qap_schedule_tables(uint64_t iters, double alpha, double* temps, hip
  * proposal's swap cost is computed in O(n) when it is met, and Delta is rebuilt
  * at the end of the call.  The run is identical whatever the split of
  * [0, iters) into calls and whichever mode is active.
- * Returns QAP_E_UNSUPPORTED when no kernel of this build handles n and the
- * value ranges, QAP_E_RANGE when info->status says so.
+ * Kernels: one workgroup holds the chain when its matrices fit one CU's LDS;
+ * otherwise (symmetric instances up to a few thousand facilities) the chain
+ * is spread over many workgroups of one cooperative launch, which needs
+ * bufs->workspace.  Returns QAP_E_UNSUPPORTED when no kernel of this build
+ * handles n and the value ranges, QAP_E_RANGE when info->status says so.
  */
-QAP_API int qap_sa_run(int32_t n, const int32_t* A, int32_t* Bp, int32_t* p, int32_t* delta,
+QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int32_t* p, int32_t* delta,
                        qap_chain_state* state, const qap_schedule* sched,
                        const qap_instance_info* info, const qap_run_buffers* bufs,
                        hipStream_t stream);
+
+/* ----------------------------------------------------------------- batches */
+
+/* One chain of a batched run.  Every pointer is a device pointer; the fields
+   copied from qap_instance_info and qap_schedule have the same meaning there. */
+typedef struct {
+    int32_t n;
+    int32_t symmetric;          /* qap_instance_info.symmetric                      */
+    int32_t a_min, a_max;       /* qap_instance_info value ranges                   */
+    int32_t b_min, b_max;
+    uint32_t flags;             /* qap_schedule.flags                               */
+    uint32_t switch_permille;   /* qap_schedule.switch_permille                     */
+    const int32_t* A;
+    int32_t* Bp;
+    int32_t* p;
+    int32_t* delta;
+    qap_chain_state* state;
+    const double* temps;        /* the chain's cooling tables (qap_schedule_tables) */
+    qap_near_tie* ties;         /* optional                                         */
+    uint32_t tie_cap;
+    uint32_t chain_id;
+    uint64_t iters;
+    uint64_t t_end;
+    double T0;
+    uint64_t seed;
+} qap_chain_desc;
+
+typedef struct {
+    int32_t threads;            /* threads per workgroup, a multiple of 64 up to 256; 0 picks 256  */
+    int32_t groups;             /* persistent workgroups; 0 fills the device (LDS permitting)     */
+    uint64_t slice;             /* > 0: every chain stops after at most this many iterations,
+                                   so one launch advances the whole batch by a slice            */
+    uint64_t* phase_cycles;     /* optional QAP_PHASES counters summed over chains              */
+} qap_batch_config;
+
+/* Bytes of device workspace qap_sa_run_batch needs (64). */
+QAP_API uint64_t qap_batch_workspace_bytes(void);
+
+/*
+ * Steps (b)-(e) of Sec. 2.2 for many independent chains of different sizes in
+ * one persistent launch.  Each workgroup repeatedly takes the next chain
+ * (order[i], or i when order is NULL) from a device-wide queue and advances it
+ * to its t_end (or by cfg->slice iterations) exactly as qap_sa_run would, so
+ * every chain's result is the same alone or in any batch and any slicing.
+ *   host_descs  host copy of the n_chains descriptors (checked, sizes the launch)
+ *   dev_descs   the same descriptors in device memory (read by the kernel)
+ *   order       optional device array of n_chains chain indices (queue order)
+ *   workspace   qap_batch_workspace_bytes() bytes of device memory
+ * Each chain must be one a single workgroup can hold (byte value ranges; n up
+ * to about 155 asymmetric or 195 symmetric); otherwise QAP_E_UNSUPPORTED.
+ * Chains in one batch must not share state, p, Bp or delta buffers.
+ */
+QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,
+                             const qap_chain_desc* dev_descs, const int32_t* order,
+                             const qap_batch_config* cfg, void* workspace, hipStream_t stream);
 
 #ifdef __cplusplus
 }

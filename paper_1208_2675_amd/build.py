@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libqapsa.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["qapsa_api.hip", "qapsa_init.hip", "qapsa_chain_lds.hip", "qapsa_chain_wg.hip"]
+SOURCES = ["qapsa_api.hip", "qapsa_init.hip", "qapsa_chain_lds.hip", "qapsa_chain_wg.hip", "qapsa_chain_dist.hip"]
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     "-ffp-contract=off", "-fno-fast-math",

@@ -42,6 +42,7 @@ QAP_API const char* qap_strerror(int status)
     case QAP_E_DEVICE: return "HIP runtime error";
     case QAP_E_UNSUPPORTED: return "no kernel in this build handles the request";
     case QAP_E_STATE: return "chain state is not ready";
+    case QAP_E_TIMEOUT: return "a grid barrier did not complete";
     default: return "unknown status";
     }
 }
@@ -63,17 +64,19 @@ QAP_API int qap_delta_init(int32_t n, const int32_t* A, const int32_t* B, const 
 
 QAP_API uint64_t qap_temp_table_len(uint64_t iters) { return temp_table_len(iters); }
 
+QAP_API uint64_t qap_workspace_bytes(int32_t n) { return n < 0 ? 0 : (uint64_t)dist_ws_bytes(n); }
+
 QAP_API int qap_schedule_tables(uint64_t iters, double alpha, double* temps, hipStream_t stream)
 {
     if (iters == 0 || !temps || !(alpha > 0.0) || alpha > 1.0) return QAP_E_INVAL;
     return launch_schedule_tables(iters, alpha, temps, stream);
 }
 
-QAP_API int qap_sa_run(int32_t n, const int32_t* A, int32_t* Bp, int32_t* p, int32_t* delta,
+QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int32_t* p, int32_t* delta,
                        qap_chain_state* state, const qap_schedule* sched,
                        const qap_instance_info* info, const qap_run_buffers* bufs, hipStream_t stream)
 {
-    if (n < 2 || n > 46340 || !A || !Bp || !p || !delta || !state || !info || !bufs || !bufs->temps)
+    if (n < 2 || n > 46340 || !A || !B || !Bp || !p || !delta || !state || !info || !bufs || !bufs->temps)
         return QAP_E_INVAL;
     const int rc = check_schedule(sched);
     if (rc != QAP_OK) return rc;
@@ -105,6 +108,37 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, int32_t* Bp, int32_t* p, int
         const int threads = n >= 48 ? 1024 : 256;
         return launch_chain_wg(a, sym, threads, stream);
     }
+    // many workgroups, one cooperative launch: symmetric byte-valued instances
+    if (bytes_ok && sym) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return QAP_E_DEVICE;
+        int G = (n + 7) / 8;                 // about eight rows per workgroup
+        if (G > cus) G = cus;
+        if (G < 2) G = 2;
+        while (G < cus && lds_dist_bytes(n, G) > budget) ++G;
+        if (lds_dist_bytes(n, G) <= budget) {
+            if (!bufs->workspace || bufs->workspace_bytes < dist_ws_bytes(n)) return QAP_E_INVAL;
+            DistArgs d{};
+            d.n = n;
+            d.a_min = info->a_min;
+            d.b_min = info->b_min;
+            d.kmin = 4096;
+            d.kmax = 1u << 22;
+            d.spin_limit = 1ull << 22;
+            d.A = A; d.B = B; d.Bp = Bp; d.p = p; d.delta = delta; d.state = state;
+            d.temps = bufs->temps;
+            d.ties = bufs->ties; d.tie_cap = bufs->tie_cap;
+            d.acc_log = a.acc_log; d.acc_cap = a.acc_cap;
+            d.prof = bufs->phase_cycles;
+            d.iters = sched->iters; d.t_end = sched->t_end; d.T0 = sched->T0;
+            d.seed = sched->seed; d.chain_id = sched->chain_id;
+            d.ws = (DistWs*)bufs->workspace;
+            d.X = (int*)((char*)bufs->workspace + sizeof(DistWs));
+            return launch_chain_dist(d, G, 512, stream);
+        }
+    }
     // 16-bit kernel (Delta mode only)
     if (!fits16(info->a_min, info->a_max) || !fits16(info->b_min, info->b_max)) return QAP_E_UNSUPPORTED;
     bool a_lds;
@@ -114,6 +148,51 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, int32_t* Bp, int32_t* p, int
     a.pitch = n | 1;
     const int threads = n >= 64 ? 1024 : 256;
     return launch_chain_lds(a, sym, a_lds, threads, stream);
+}
+
+QAP_API uint64_t qap_batch_workspace_bytes(void) { return sizeof(BatchWs); }
+
+QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs, const qap_chain_desc* dev_descs,
+                             const int32_t* order, const qap_batch_config* cfg, void* workspace,
+                             hipStream_t stream)
+{
+    if (n_chains < 0 || (n_chains > 0 && (!host_descs || !dev_descs)) || !cfg || !workspace) return QAP_E_INVAL;
+    if (n_chains == 0) return QAP_OK;
+    const int threads = cfg->threads ? cfg->threads : 256;
+    if (threads < 64 || threads > 256 || threads % 64) return QAP_E_INVAL;
+    size_t lds = 0;
+    for (int i = 0; i < n_chains; ++i) {
+        const qap_chain_desc& d = host_descs[i];
+        if (d.n < 2 || d.n > 46340 || !d.A || !d.Bp || !d.p || !d.delta || !d.state || !d.temps) return QAP_E_INVAL;
+        if (d.iters == 0 || d.t_end > d.iters || !(d.T0 > 0.0)) return QAP_E_INVAL;
+        if ((d.flags & ~(QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY)) != 0 || d.switch_permille > 1000)
+            return QAP_E_INVAL;
+        if ((int64_t)d.a_max - d.a_min > 255 || (int64_t)d.b_max - d.b_min > 255) return QAP_E_UNSUPPORTED;
+        const size_t b = lds_wg_bytes(d.n, d.symmetric != 0);
+        if (b > kLdsLimit - kLdsStaticReserve) return QAP_E_UNSUPPORTED;
+        if (b > lds) lds = b;
+    }
+    int groups = cfg->groups;
+    if (groups <= 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return QAP_E_DEVICE;
+        const size_t per_cu_lds = (kLdsLimit) / (lds + kLdsStaticReserve);
+        const size_t per_cu_waves = 32 / (threads / 64);   // 8 waves per SIMD
+        size_t per_cu = per_cu_lds < per_cu_waves ? per_cu_lds : per_cu_waves;
+        if (per_cu < 1) per_cu = 1;
+        groups = (int)((size_t)cus * per_cu);
+    }
+    if (groups > n_chains) groups = n_chains;
+    BatchArgs b{};
+    b.n_chains = n_chains;
+    b.descs = dev_descs;
+    b.order = order;
+    b.ws = (BatchWs*)workspace;
+    b.slice = cfg->slice;
+    b.prof = cfg->phase_cycles;
+    return launch_chain_batch(b, groups, threads, lds, stream);
 }
 
 }  // extern "C"

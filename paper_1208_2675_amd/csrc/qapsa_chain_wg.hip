@@ -727,7 +727,62 @@ __global__ void __launch_bounds__(1024) k_chain_wg(ChainArgs a)
     chain_run<SYM>(a, smem);
 }
 
+// Many independent chains in one persistent launch: each workgroup takes the
+// next chain from a device-wide queue and runs it (or its next slice) with the
+// one-workgroup routine above.
+__global__ void __launch_bounds__(256) k_chain_batch(BatchArgs b)
+{
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int s_idx;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = (int)atomicAdd(&b.ws->next, 1u);
+        __syncthreads();
+        const int idx = s_idx;
+        __syncthreads();
+        if (idx >= b.n_chains) break;
+        const int c = b.order ? b.order[idx] : idx;
+        const qap_chain_desc d = b.descs[c];
+        ChainArgs a{};
+        a.n = d.n;
+        a.quads = ((d.n + 3) / 4) | 1;
+        a.max_step = 16;
+        a.flags = d.flags;
+        a.switch_permille = d.switch_permille ? d.switch_permille : 20;
+        a.a_min = d.a_min;
+        a.b_min = d.b_min;
+        a.A = d.A; a.Bp = d.Bp; a.p = d.p; a.delta = d.delta; a.state = d.state;
+        a.temps = d.temps;
+        a.ties = d.ties; a.tie_cap = d.tie_cap;
+        a.prof = b.prof;
+        a.iters = d.iters;
+        const uint64_t t_now = d.state->t;
+        a.t_end = (b.slice && t_now + b.slice < d.t_end) ? t_now + b.slice : d.t_end;
+        if (a.t_end < t_now) a.t_end = t_now;
+        a.T0 = d.T0;
+        a.seed = d.seed;
+        a.chain_id = d.chain_id;
+        if (d.symmetric) chain_run<true>(a, smem);
+        else chain_run<false>(a, smem);
+        __syncthreads();
+    }
+}
+
+__global__ void k_batch_reset(BatchWs* ws) { ws->next = 0; }
+
 }  // namespace
+
+int launch_chain_batch(const BatchArgs& b, int groups, int threads, size_t lds_bytes, hipStream_t stream)
+{
+    const void* fn = (const void*)k_chain_batch;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess)
+        return QAP_E_DEVICE;
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, stream, b.ws);
+    BatchArgs args = b;
+    void* kargs[] = {&args};
+    if (hipLaunchKernel(fn, dim3(groups), dim3(threads), kargs, lds_bytes, stream) != hipSuccess)
+        return QAP_E_DEVICE;
+    return QAP_OK;
+}
 
 int wg_quads(int n)
 {

@@ -47,7 +47,7 @@ struct ChainArgs {
 // LDS footprint (bytes) of the one-workgroup chain kernel.
 size_t lds_chain_bytes(int n, bool symmetric, bool a_in_lds);
 constexpr size_t kLdsLimit = 160 * 1024;
-constexpr size_t kLdsStaticReserve = 512;   // the kernel's static __shared__ scalars
+constexpr size_t kLdsStaticReserve = 2048;  // the kernels' static __shared__ variables
 
 int launch_cost(int n, const int32_t* A, const int32_t* B, const int32_t* p, int64_t* cost,
                 hipStream_t stream);
@@ -57,6 +57,65 @@ int launch_delta_init(int n, const int32_t* A, const int32_t* B, const int32_t* 
 int launch_schedule_tables(uint64_t iters, double alpha, double* temps, hipStream_t stream);
 int launch_chain_lds(const ChainArgs& a, bool symmetric, bool a_in_lds, int threads,
                      hipStream_t stream);
+
+// Global workspace of the multi-workgroup kernel (one per chain, caller memory).
+struct DistWs {
+    unsigned long long count;    // grid barrier arrivals
+    unsigned long long key[3];   // first acceptance of a scan window, min-reduced
+    unsigned long long nties;    // near ties logged by this call
+    int err;                     // a barrier timed out
+    int pad[5];
+};
+static_assert(sizeof(DistWs) == 64, "workspace header");
+
+inline size_t dist_ws_bytes(int n) { return sizeof(DistWs) + 4 * sizeof(int) * (size_t)n; }
+
+struct DistArgs {
+    int32_t n;
+    int32_t quads;
+    int32_t a_min, b_min;
+    uint32_t kmin, kmax;         // scan window bounds (proposals)
+    uint64_t spin_limit;         // barrier polls before giving up
+    const int32_t* A;
+    const int32_t* B;
+    int32_t* Bp;
+    int32_t* p;
+    int32_t* delta;
+    qap_chain_state* state;
+    const double* temps;
+    qap_near_tie* ties;
+    int64_t* acc_log;
+    uint64_t acc_cap;
+    uint64_t* prof;
+    uint64_t iters;
+    uint64_t t_end;
+    double T0;
+    uint64_t seed;
+    uint32_t chain_id;
+    uint32_t tie_cap;
+    DistWs* ws;
+    int* X;
+};
+
+int dist_quads(int n);
+size_t lds_dist_bytes(int n, int G);
+int launch_chain_dist(const DistArgs& a, int G, int threads, hipStream_t stream);
+
+// batched chains (one persistent launch, a device-wide work queue)
+struct BatchWs {
+    unsigned next;
+    unsigned pad[15];
+};
+struct BatchArgs {
+    int32_t n_chains;
+    int32_t pad;
+    const qap_chain_desc* descs;
+    const int32_t* order;
+    BatchWs* ws;
+    uint64_t slice;
+    uint64_t* prof;
+};
+int launch_chain_batch(const BatchArgs& b, int groups, int threads, size_t lds_bytes, hipStream_t stream);
 
 // byte-valued chain kernel (scratch and Delta modes)
 int wg_quads(int n);

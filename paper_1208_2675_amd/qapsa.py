@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqapsa.so")
 
 QAP_OK, QAP_E_INVAL, QAP_E_NOT_PERM, QAP_E_RANGE = 0, -1, -2, -3
-QAP_E_NOMEM, QAP_E_DEVICE, QAP_E_UNSUPPORTED, QAP_E_STATE = -4, -5, -6, -7
+QAP_E_NOMEM, QAP_E_DEVICE, QAP_E_UNSUPPORTED, QAP_E_STATE, QAP_E_TIMEOUT = -4, -5, -6, -7, -8
 QAP_MODE_SCRATCH, QAP_MODE_DELTA = 0, 1
 QAP_FLAG_DELTA_ONLY, QAP_FLAG_SCRATCH_ONLY = 1, 2
 
@@ -56,7 +56,7 @@ class Schedule(C.Structure):
 class RunBuffers(C.Structure):
     _fields_ = [("temps", C.c_void_p), ("ties", C.c_void_p), ("tie_cap", C.c_uint32),
                 ("reserved", C.c_uint32), ("accept_log", C.c_void_p), ("accept_cap", C.c_uint64),
-                ("phase_cycles", C.c_void_p)]
+                ("phase_cycles", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64)]
 
 
 PHASES = ["total", "scratch_thresh", "scratch_eval", "scratch_accept", "delta_scan", "delta_update", "build",
@@ -84,7 +84,9 @@ def _load():
     L.qap_temp_table_len.restype = u64
     L.qap_schedule_tables.argtypes = [u64, C.c_double, vp, vp]
     L.qap_schedule_tables.restype = C.c_int
-    L.qap_sa_run.argtypes = [i32, vp, vp, vp, vp, vp, C.POINTER(Schedule), C.POINTER(InstanceInfo),
+    L.qap_workspace_bytes.argtypes = [i32]
+    L.qap_workspace_bytes.restype = u64
+    L.qap_sa_run.argtypes = [i32, vp, vp, vp, vp, vp, vp, C.POINTER(Schedule), C.POINTER(InstanceInfo),
                              C.POINTER(RunBuffers), vp]
     L.qap_sa_run.restype = C.c_int
     return L
@@ -138,9 +140,13 @@ def qap_schedule_tables(iters, alpha, temps, stream=None) -> int:
     return _lib.qap_schedule_tables(iters, alpha, _ptr(temps), _stream(stream))
 
 
-def qap_sa_run(n, A, Bp, p, delta, state, sched: Schedule, info: InstanceInfo, bufs: RunBuffers,
+def qap_workspace_bytes(n: int) -> int:
+    return int(_lib.qap_workspace_bytes(n))
+
+
+def qap_sa_run(n, A, B, Bp, p, delta, state, sched: Schedule, info: InstanceInfo, bufs: RunBuffers,
                stream=None) -> int:
-    return _lib.qap_sa_run(n, _ptr(A), _ptr(Bp), _ptr(p), _ptr(delta), _ptr(state), C.byref(sched),
+    return _lib.qap_sa_run(n, _ptr(A), _ptr(B), _ptr(Bp), _ptr(p), _ptr(delta), _ptr(state), C.byref(sched),
                            C.byref(info), C.byref(bufs), _stream(stream))
 
 
@@ -191,6 +197,7 @@ class Chain:
         self.accept_cap = accept_cap
         self.accept_log = torch.zeros((max(accept_cap, 1), 4), dtype=torch.int64, device=dev)
         self.prof = torch.zeros(len(PHASES), dtype=torch.int64, device=dev) if profile else None
+        self.workspace = torch.zeros(qap_workspace_bytes(n), dtype=torch.uint8, device=dev)
         self.info = None
         self.sched = None
 
@@ -212,7 +219,8 @@ class Chain:
     def buffers(self) -> RunBuffers:
         return RunBuffers(self.temps.data_ptr(), self.ties.data_ptr(), self.tie_cap, 0,
                           self.accept_log.data_ptr() if self.accept_cap else None, self.accept_cap,
-                          self.prof.data_ptr() if self.prof is not None else None)
+                          self.prof.data_ptr() if self.prof is not None else None,
+                          self.workspace.data_ptr(), self.workspace.numel())
 
     def phases(self) -> dict:
         """Phase counters of the runs so far (cycles of the shader clock, counts)."""
@@ -221,8 +229,8 @@ class Chain:
 
     def run(self, t_end: int | None = None):
         self.sched.t_end = self.iters if t_end is None else int(t_end)
-        _check(qap_sa_run(self.n, self.A, self.Bp, self.p, self.delta, self.state_d, self.sched, self.info,
-                          self.buffers(), self.stream), "qap_sa_run")
+        _check(qap_sa_run(self.n, self.A, self.B, self.Bp, self.p, self.delta, self.state_d, self.sched,
+                          self.info, self.buffers(), self.stream), "qap_sa_run")
         return self
 
     def state(self) -> ChainState:
@@ -246,3 +254,137 @@ class Chain:
         if self.accept_cap:
             out["accept_log"] = self.accept_log.cpu().numpy()[: min(st.accepts, self.accept_cap)]
         return out
+
+
+# ------------------------------------------------------------------ batches
+
+class ChainDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("symmetric", C.c_int32), ("a_min", C.c_int32), ("a_max", C.c_int32),
+                ("b_min", C.c_int32), ("b_max", C.c_int32), ("flags", C.c_uint32), ("switch_permille", C.c_uint32),
+                ("A", C.c_void_p), ("Bp", C.c_void_p), ("p", C.c_void_p), ("delta", C.c_void_p),
+                ("state", C.c_void_p), ("temps", C.c_void_p), ("ties", C.c_void_p), ("tie_cap", C.c_uint32),
+                ("chain_id", C.c_uint32), ("iters", C.c_uint64), ("t_end", C.c_uint64), ("T0", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("groups", C.c_int32), ("slice", C.c_uint64),
+                ("phase_cycles", C.c_void_p)]
+
+
+_lib.qap_batch_workspace_bytes.argtypes = []
+_lib.qap_batch_workspace_bytes.restype = C.c_uint64
+_lib.qap_sa_run_batch.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(BatchConfig),
+                                  C.c_void_p, C.c_void_p]
+_lib.qap_sa_run_batch.restype = C.c_int
+
+
+def qap_batch_workspace_bytes() -> int:
+    return int(_lib.qap_batch_workspace_bytes())
+
+
+def qap_sa_run_batch(n_chains, host_descs, dev_descs, order, cfg: BatchConfig, workspace, stream=None) -> int:
+    return _lib.qap_sa_run_batch(n_chains, C.cast(host_descs, C.c_void_p) if host_descs is not None else None,
+                                 _ptr(dev_descs), _ptr(order), C.byref(cfg), _ptr(workspace), _stream(stream))
+
+
+class Batch:
+    """Device buffers of many independent chains and one batched run.
+
+    ``chains`` are workload chains (A, B, p0, iters, philox_seed, chain_id);
+    chains that share the same A array object share its device copy.
+    """
+
+    def __init__(self, chains, device: str = "cuda", tie_cap: int = 16, profile: bool = False):
+        import torch
+        self.torch = torch
+        dev = torch.device(device)
+        self.chains = chains
+        self.k = len(chains)
+        inst = {}
+        self.views = []
+        for ch in chains:
+            key = (id(ch.A), id(ch.B))
+            if key not in inst:
+                inst[key] = (torch.from_numpy(np.ascontiguousarray(ch.A, dtype=np.int32)).to(dev),
+                             torch.from_numpy(np.ascontiguousarray(ch.B, dtype=np.int32)).to(dev))
+            self.views.append(inst[key])
+        n_tot = sum(ch.n for ch in chains)
+        m_tot = sum(max(ch.n * (ch.n - 1) // 2, 1) for ch in chains)
+        self.p = torch.empty(n_tot, dtype=torch.int32, device=dev)
+        self.Bp = torch.empty(sum(ch.n * ch.n for ch in chains), dtype=torch.int32, device=dev)
+        self.delta = torch.empty(m_tot, dtype=torch.int32, device=dev)
+        self.info_d = torch.zeros((self.k, INFO_BYTES), dtype=torch.uint8, device=dev)
+        self.state_d = torch.zeros((self.k, STATE_BYTES), dtype=torch.uint8, device=dev)
+        t_tot = sum(qap_temp_table_len(ch.iters) for ch in chains)
+        self.temps = torch.empty(t_tot, dtype=torch.float64, device=dev)
+        self.tie_cap = tie_cap
+        self.ties = torch.zeros((self.k, max(tie_cap, 1) * TIE_BYTES), dtype=torch.uint8, device=dev)
+        self.ws = torch.zeros(qap_batch_workspace_bytes(), dtype=torch.uint8, device=dev)
+        self.prof = torch.zeros(len(PHASES), dtype=torch.int64, device=dev) if profile else None
+        self.off = []
+        po = bo = do = to = 0
+        for ch in chains:
+            self.off.append((po, bo, do, to))
+            po += ch.n; bo += ch.n * ch.n; do += max(ch.n * (ch.n - 1) // 2, 1); to += qap_temp_table_len(ch.iters)
+        self.p.copy_(torch.from_numpy(np.concatenate([np.asarray(ch.p0, dtype=np.int32) for ch in chains])).to(dev))
+        self.descs = None
+
+    def init(self, ratio: float = 1e-3, flags: int = 0, switch_permille: int = 0):
+        torch = self.torch
+        i4, i8, f8 = 4, 8, 8
+        for i, ch in enumerate(self.chains):
+            A, B = self.views[i]
+            po, bo, do, _ = self.off[i]
+            _check(qap_delta_init(ch.n, A, B, self.p.data_ptr() + i4 * po, self.Bp.data_ptr() + i4 * bo,
+                                  self.delta.data_ptr() + i4 * do, self.info_d[i], self.state_d[i]),
+                   "qap_delta_init")
+        torch.cuda.synchronize()
+        raw = self.info_d.cpu().numpy()
+        self.infos = [InstanceInfo.from_buffer_copy(raw[i].tobytes()) for i in range(self.k)]
+        descs = (ChainDesc * self.k)()
+        for i, ch in enumerate(self.chains):
+            inf = self.infos[i]
+            if inf.status != QAP_OK:
+                raise QapError(inf.status, f"qap_delta_init (device), chain {i}")
+            po, bo, do, to = self.off[i]
+            m = ch.n * (ch.n - 1) // 2
+            T0 = float(inf.sum_abs_delta) / float(m)
+            alpha = geometric_alpha(ch.iters, ratio)
+            temps = self.temps.data_ptr() + f8 * to
+            _check(qap_schedule_tables(ch.iters, alpha, temps), "qap_schedule_tables")
+            A, _ = self.views[i]
+            descs[i] = ChainDesc(ch.n, inf.symmetric, inf.a_min, inf.a_max, inf.b_min, inf.b_max, flags,
+                                 switch_permille, A.data_ptr(), self.Bp.data_ptr() + i4 * bo,
+                                 self.p.data_ptr() + i4 * po, self.delta.data_ptr() + i4 * do,
+                                 self.state_d[i].data_ptr(), temps, self.ties[i].data_ptr(), self.tie_cap,
+                                 ch.chain_id, ch.iters, ch.iters, T0, ch.philox_seed & (2**64 - 1))
+        self.descs = descs
+        raw = np.frombuffer(bytes(descs), dtype=np.uint8).copy()
+        self.descs_d = torch.from_numpy(raw).to(self.p.device)
+        return self
+
+    def run(self, threads: int = 256, groups: int = 0, slice_iters: int = 0, order=None, stream=None):
+        cfg = BatchConfig(threads, groups, slice_iters, self.prof.data_ptr() if self.prof is not None else None)
+        _check(qap_sa_run_batch(self.k, self.descs, self.descs_d, order, cfg, self.ws, stream), "qap_sa_run_batch")
+        return self
+
+    def states(self) -> list[dict]:
+        self.torch.cuda.synchronize()
+        raw = self.state_d.cpu().numpy()
+        out = []
+        for i in range(self.k):
+            st = ChainState.from_buffer_copy(raw[i].tobytes())
+            out.append({k: int(getattr(st, k)) for k, _ in ChainState._fields_})
+        return out
+
+    def perm(self, i: int) -> np.ndarray:
+        po = self.off[i][0]
+        return self.p[po: po + self.chains[i].n].cpu().numpy()
+
+    def done(self) -> bool:
+        return all(s["t"] >= ch.iters for s, ch in zip(self.states(), self.chains))
+
+    def phases(self) -> dict:
+        v = self.prof.cpu().numpy().tolist()
+        return {k: int(x) for k, x in zip(PHASES, v) if k != "reserved"}

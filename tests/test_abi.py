@@ -28,8 +28,8 @@ def qlib():
 
 def test_header_declares_the_boundary():
     names = set(_declared())
-    assert {"qap_strerror", "qap_cost", "qap_delta_init", "qap_temp_table_len",
-            "qap_schedule_tables", "qap_sa_run"} <= names
+    assert {"qap_strerror", "qap_cost", "qap_delta_init", "qap_temp_table_len", "qap_workspace_bytes",
+            "qap_schedule_tables", "qap_sa_run", "qap_batch_workspace_bytes", "qap_sa_run_batch"} <= names
 
 
 def test_every_declared_symbol_is_exported(qlib):
@@ -41,17 +41,19 @@ def test_struct_layout_matches_binding(tmp_path):
     from paper_1208_2675_amd import qapsa as Q
     src = tmp_path / "sz.c"
     src.write_text('#include "qapsa.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\","
+                   "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
                    "sizeof(qap_instance_info), sizeof(qap_chain_state), sizeof(qap_near_tie),"
                    "sizeof(qap_schedule), sizeof(qap_run_buffers), offsetof(qap_chain_state, status),"
-                   "offsetof(qap_run_buffers, accept_log));return 0;}\n")
+                   "offsetof(qap_run_buffers, workspace), sizeof(qap_chain_desc), offsetof(qap_chain_desc, T0),"
+                   "sizeof(qap_batch_config));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
                     "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert got == [C.sizeof(Q.InstanceInfo), C.sizeof(Q.ChainState), C.sizeof(Q.NearTie),
                    C.sizeof(Q.Schedule), C.sizeof(Q.RunBuffers), Q.ChainState.status.offset,
-                   Q.RunBuffers.accept_log.offset]
+                   Q.RunBuffers.workspace.offset, C.sizeof(Q.ChainDesc), Q.ChainDesc.T0.offset,
+                   C.sizeof(Q.BatchConfig)]
 
 
 def test_host_side_argument_errors(qlib):
@@ -60,26 +62,29 @@ def test_host_side_argument_errors(qlib):
     assert Q.qap_strerror(Q.QAP_E_RANGE).startswith("instance values")
     assert Q.qap_temp_table_len(10**9) == 2048 + 954
     assert Q.qap_temp_table_len(1) == 2049
+    assert Q.qap_workspace_bytes(2000) == 64 + 16 * 2000
     fake = 0x1000  # never dereferenced: every call below is rejected first
+    assert Q.qap_sa_run(8, fake, None, fake, fake, fake, fake, Q.Schedule(100, 100, 1.0, 0.99, 1, 0, 0, 0, 0),
+                        Q.InstanceInfo(0, 0, 0, 9, 0, 9, 1, 0), Q.RunBuffers(fake, None, 0, 0, None, 0), 0) == Q.QAP_E_INVAL
     info = Q.InstanceInfo(0, 0, 0, 9, 0, 9, 1, 0)
     bufs = Q.RunBuffers(fake, None, 0, 0, None, 0)
     ok = Q.Schedule(100, 100, 1.0, 0.99, 1, 0, 0, 0, 0)
-    assert Q.qap_sa_run(1, fake, fake, fake, fake, fake, ok, info, bufs, 0) == Q.QAP_E_INVAL
+    assert Q.qap_sa_run(1, fake, fake, fake, fake, fake, fake, ok, info, bufs, 0) == Q.QAP_E_INVAL
     for bad in (Q.Schedule(100, 101, 1.0, 0.99, 1, 0, 0, 0, 0), Q.Schedule(100, 100, 0.0, 0.99, 1, 0, 0, 0, 0),
                 Q.Schedule(100, 100, float("nan"), 0.99, 1, 0, 0, 0, 0),
                 Q.Schedule(100, 100, 1.0, 1.5, 1, 0, 0, 0, 0), Q.Schedule(0, 0, 1.0, 0.5, 1, 0, 0, 0, 0),
                 Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 7, 0, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 3, 0, 0),
                 Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 0, 1001, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 0, 0, 1)):
-        assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, bad, info, bufs, 0) == Q.QAP_E_INVAL
-    assert Q.qap_sa_run(8, fake, None, fake, fake, fake, ok, info, bufs, 0) == Q.QAP_E_INVAL
-    assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, ok, info, Q.RunBuffers(None, None, 0, 0, None, 0),
+        assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, fake, bad, info, bufs, 0) == Q.QAP_E_INVAL
+    assert Q.qap_sa_run(8, fake, fake, None, fake, fake, fake, ok, info, bufs, 0) == Q.QAP_E_INVAL
+    assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, fake, ok, info, Q.RunBuffers(None, None, 0, 0, None, 0),
                         0) == Q.QAP_E_INVAL
     # a device-reported error in the instance facts is passed through
     bad_info = Q.InstanceInfo(0, 0, 0, 9, 0, 9, 1, Q.QAP_E_RANGE)
-    assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, ok, bad_info, bufs, 0) == Q.QAP_E_RANGE
+    assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, fake, ok, bad_info, bufs, 0) == Q.QAP_E_RANGE
     # values outside the 16-bit working range have no single-workgroup kernel
     wide = Q.InstanceInfo(0, 0, 0, 70000, 0, 9, 1, 0)
-    assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, ok, wide, bufs, 0) == Q.QAP_E_UNSUPPORTED
+    assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, fake, ok, wide, bufs, 0) == Q.QAP_E_UNSUPPORTED
     assert Q.qap_cost(0, fake, fake, fake, fake, 0) == Q.QAP_E_INVAL
     assert Q.qap_delta_init(1, fake, fake, fake, fake, fake, fake, None, 0) == Q.QAP_E_INVAL
     assert Q.qap_schedule_tables(0, 0.5, fake, 0) == Q.QAP_E_INVAL

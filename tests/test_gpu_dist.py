@@ -1,0 +1,94 @@
+"""Parity of the multi-workgroup chain kernel (symmetric instances too large
+for one CU) with the CPU oracle, and at N=2000 against stored oracle results."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1208_2675_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_runs.json")
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1208_2675_amd import qapsa
+    return qapsa
+
+
+def _sym(n, seed, hi=99):
+    rng = np.random.default_rng(seed)
+    A = np.triu(rng.integers(0, hi + 1, (n, n)), 1)
+    B = np.triu(rng.integers(0, hi + 1, (n, n)), 1)
+    return (A + A.T).astype(np.int32), (B + B.T).astype(np.int32), rng.permutation(n).astype(np.int32)
+
+
+def _run_compare(orc, Q, A, B, p0, iters, seed, T0=None, slices=(), acc_cap=512, check_delta=True):
+    n = A.shape[0]
+    print(f"[case] dist n={n} iters={iters} seed={seed} T0={T0} slices={slices}", flush=True)
+    s = orc.schedule(A, B, p0, iters)
+    T0o = s["T0"] if T0 is None else T0
+    ref = orc.sa_run(A, B, p0, iters, T0o, s["alpha"], seed, 0, acc_cap=acc_cap, tie_cap=64)
+    c = Q.Chain(A, B, p0, iters, seed, 0, T0=T0, accept_cap=acc_cap).init()
+    for t_end in list(slices) + [iters]:
+        c.run(t_end)
+    got = c.result(with_delta=True)
+    assert got["status"] == 0 and got["mode"] == Q.QAP_MODE_DELTA
+    for k in ("t", "accepts", "hash", "cost", "best_cost", "best_iter", "near_ties"):
+        assert got[k] == ref[k], (k, got[k], ref[k])
+    assert np.array_equal(got["p"], ref["p"])
+    assert np.array_equal(got["accept_log"], ref["accept_log"])
+    assert np.array_equal(got["Bp"], B[np.ix_(got["p"], got["p"])])
+    if check_delta:
+        assert np.array_equal(got["delta"], orc.delta_matrix(A, B, got["p"]))
+    return got
+
+
+@pytest.mark.parametrize("n,iters", [(201, 30000), (260, 40000), (333, 40000), (517, 30000)])
+def test_dist_matches_oracle(orc, Q, n, iters):
+    A, B, p0 = _sym(n, 500 + n)
+    _run_compare(orc, Q, A, B, p0, iters, seed=7 + n)
+
+
+def test_dist_infinite_temperature(orc, Q):
+    A, B, p0 = _sym(300, 61)
+    got = _run_compare(orc, Q, A, B, p0, 3000, seed=1, T0=math.inf, acc_cap=3000)
+    assert got["accepts"] == 3000
+
+
+def test_dist_slices(orc, Q):
+    A, B, p0 = _sym(280, 62)
+    _run_compare(orc, Q, A, B, p0, 30000, seed=2, slices=(1, 999, 15000, 15001))
+
+
+def test_dist_low_temperature(orc, Q):
+    A, B, p0 = _sym(240, 63)
+    _run_compare(orc, Q, A, B, p0, 200000, seed=3, T0=1.0)
+
+
+def test_dist_n2000_prefix_golden(orc, Q):
+    with open(GOLD) as f:
+        g = json.load(f)["n2000_sym@2000000"]
+    ch = W.single_chain("n2000_sym")
+    c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id).init()
+    assert c.sched.T0 == g["T0"] and c.sched.alpha == g["alpha"]
+    assert c.info.sum_abs_delta == g["sum_abs_delta0"] and c.info.cost == g["cost0"]
+    c.run(2_000_000)
+    r = c.result(with_delta=True)
+    for k in ("accepts", "hash", "cost", "best_cost", "best_iter", "near_ties"):
+        assert r[k] == g[k], (k, r[k], g[k])
+    assert r["t"] == g["t_end"]
+    assert r["p"].tolist() == g["p"]
+    # sampled Delta entries equal the definition at the final p
+    rng = np.random.default_rng(1)
+    n = ch.n
+    for _ in range(300):
+        a_, b_ = sorted(rng.choice(n, 2, replace=False))
+        idx = a_ * (2 * n - a_ - 1) // 2 + b_ - a_ - 1
+        assert r["delta"][idx] == orc.swap_cost(ch.A, ch.B, r["p"], int(a_), int(b_))
