@@ -1,18 +1,32 @@
 """Benchmark: simulated-annealing iterations/s and accepted-swap Delta-updates/s
-of the HIP path on one MI355X, with the CPU oracle timed beside it.
+of the HIP path on one MI355X, single chain vs batched chains, with the CPU
+oracle timed beside it.
 
-    python bench.py [--steps K] [--warmup W] [--workload n150_asym]
+    python bench.py [--steps K] [--warmup W] [--sections single,batched,update,serve]
 
-One step is one whole annealing run of the workload (set-up of B', Delta,
-cost and schedule, then all I iterations) on inputs already resident in device
-memory.  The default workload is the single chain on the N=150 asymmetric
-instance (sparse flows, 10 x 15 Manhattan grid), I = 1e8, geometric cooling
-from T0 = mean |Delta_0| to T0 * 1e-3.  Prints one JSON line.
+Headline (``value``): one step is one whole annealing run of the single-chain
+workload -- set-up of B', Delta, cost and schedule, then all I iterations -- on
+inputs already resident in device memory.  The workload is the N=150
+asymmetric instance (sparse flows on a 10 x 15 Manhattan grid), I = 1e8,
+geometric cooling from T0 = mean |Delta_0| to 1e-3 T0.
+
+Further sections, reported in the same JSON line:
+  batched  512 chains over 64 instances of N in [20, 200], I = 1e7 each, in one
+           persistent launch; aggregate iterations/s and the ratio to the
+           single-chain rate.
+  update   the Delta update at N = 2000 (symmetric, Euclidean distances) with
+           every proposal accepted (T = +inf): updates/s and the roofline of
+           the multi-workgroup kernel against HBM (algorithmic int32 bytes per
+           update: 4N(N-1) for Delta read + write, 8N^2 for A and B' read once).
+  serve    a prefix of the served trace (Poisson 200 req/s, N log-uniform in
+           [32, 512], I = 1e7): p50/p99 latency and aggregate iterations/s.
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -24,10 +38,13 @@ HBM_PEAK_GBS = 8000.0
 
 
 def update_bytes(n: int, symmetric: bool) -> int:
-    """Algorithmic bytes of one Delta update with int32 entries: read and write
-    the n(n-1)/2 packed Delta entries, read A and B' once each (twice each,
-    rows and columns, for an asymmetric instance)."""
+    """Algorithmic bytes of one Delta update, int32 entries: read and write the
+    n(n-1)/2 packed entries; read A and B' once (rows and columns when asymmetric)."""
     return 4 * n * (n - 1) + (8 if symmetric else 16) * n * n
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(ch, iters_sample: int) -> dict:
@@ -39,32 +56,14 @@ def cpu_baseline(ch, iters_sample: int) -> dict:
                       t_end=iters_sample)
     dt = time.perf_counter() - t0
     return {"value": iters_sample / dt, "unit": "iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {iters_sample:.0e} iterations of the same schedule (single thread, "
-                      f"{r['accepts']} accepts, {dt:.1f} s); the oracle's cost per iteration does not "
-                      f"depend on the acceptance rate"}
+            "sample": f"first {iters_sample:.0e} iterations of the same schedule, single thread "
+                      f"({r['accepts']} accepts, {dt:.1f} s); the oracle computes every proposal's swap cost "
+                      f"from scratch, so its cost per iteration does not depend on the acceptance rate"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n150_asym")
-    ap.add_argument("--cpu-sample", type=int, default=30_000_000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(independent chains shard across GPUs without communication, see the design notes)",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_1208_2675_amd import qapsa as Q
-    from paper_1208_2675_amd import workloads as W
-
+def section_single(Q, W, torch, args):
     ch = W.single_chain(args.workload)
-    print(f"[bench] workload={args.workload} n={ch.n} iters={ch.iters}", file=sys.stderr, flush=True)
+    log(f"single: workload={args.workload} n={ch.n} iters={ch.iters}")
     c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id)
     p0 = c.p.clone()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -85,12 +84,7 @@ def main():
     results = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-
     st = results[-1][0]
-    kernel_ms = sum(r[1] for r in results) / len(results)
-    iters_total = ch.iters * args.steps
-    accepts_total = sum(int(r[0].accepts) for r in results)
-    value = iters_total / wall
     parity = None
     gold_path = os.path.join(ROOT, "tests", "golden", "oracle_runs.json")
     key = f"{args.workload}@{ch.iters}"
@@ -99,9 +93,113 @@ def main():
         if g:
             parity = all(int(getattr(st, k)) == g[k] for k in ("accepts", "hash", "cost", "best_cost")) and \
                 c.p.cpu().numpy().tolist() == g["p"]
+    # phase split from one profiled run (not timed)
+    cp = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id, profile=True).init().run()
+    phases = cp.phases()
+    return {
+        "ch": ch, "wall": wall, "iters_total": ch.iters * args.steps,
+        "accepts_total": sum(int(r[0].accepts) for r in results), "state": st,
+        "kernel_ms": sum(r[1] for r in results) / len(results), "parity": parity, "phases": phases,
+        "symmetric": bool(c.info.symmetric),
+    }
 
-    sym = bool(c.info.symmetric)
-    achieved = int(st.accepts) * update_bytes(ch.n, sym) / (kernel_ms * 1e-3) / 1e9
+
+def section_batched(Q, W, torch, args):
+    chains = W.batched_mix(iters=args.batch_iters)
+    fits = [ch for ch in chains
+            if Q.fits_one_workgroup(ch.n, ch.symmetric, int(ch.A.max() - ch.A.min()), int(ch.B.max() - ch.B.min()))]
+    log(f"batched: {len(fits)} of {len(chains)} chains, I={args.batch_iters:.0e}")
+    b = Q.Batch(fits).init()
+    # largest expected work first
+    import numpy as np
+    order = torch.tensor(np.argsort([-(ch.n * ch.n) for ch in fits]).astype(np.int32), device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    b.run(threads=args.batch_threads, order=order)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sts = b.states()
+    iters = sum(ch.iters for ch in fits)
+    acc = sum(s["accepts"] for s in sts)
+    return {"chains": len(fits), "chains_total": len(chains), "iters": iters, "wall_s": wall,
+            "kernel_ms": ev0.elapsed_time(ev1), "value": iters / wall, "delta_updates_per_s": acc / wall,
+            "unsupported_chains": len(chains) - len(fits)}
+
+
+def section_update(Q, W, torch, args):
+    ch = W.single_chain("n2000_sym")
+    n = ch.n
+    k = args.update_accepts
+    log(f"update: n={n} forced accepts={k}")
+    c = Q.Chain(ch.A, ch.B, ch.p0, k, ch.philox_seed, ch.chain_id, T0=math.inf)
+    c.init()
+    c.run(16)                                   # warm: load, one window
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    c.run(k)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    st = c.state()
+    ups = (k - 16) / (ms * 1e-3)
+    per = update_bytes(n, True)
+    achieved = per * ups / 1e9
+    return {"n": n, "updates": k - 16, "kernel_ms": ms, "updates_per_s": ups, "us_per_update": 1e6 / ups,
+            "bytes_per_update": per, "achieved_GBs": achieved, "accepts": int(st.accepts), "status": int(st.status)}
+
+
+def section_serve(Q, W, torch, args):
+    from paper_1208_2675_amd.serve import Server
+    reqs = W.served_trace(n_requests=args.serve_requests, iters=args.serve_iters)
+    log(f"serve: {len(reqs)} requests, I={args.serve_iters:.0e}, slice={args.serve_slice}")
+    srv = Server(max_slots=args.serve_slots, memory_budget=args.serve_budget, slice_iters=args.serve_slice)
+    st = srv.run_trace(reqs, time_limit=args.serve_time_limit)
+    import numpy as np
+    lat = np.array([r.latency for r in st.results]) if st.results else np.array([float("nan")])
+    return {"requests": len(reqs), "completed": len(st.results), "wall_s": st.wall_s,
+            "iterations_per_s": st.iterations / st.wall_s, "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "slices": st.slices,
+            "mean_resident": st.resident_sum / max(st.slices, 1), "waits_for_memory": st.waits_for_memory,
+            "offered_iterations_per_s": 200.0 * args.serve_iters}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="n150_asym")
+    ap.add_argument("--sections", default="single,batched,update,serve")
+    ap.add_argument("--cpu-sample", type=int, default=30_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-iters", type=int, default=10**7)
+    ap.add_argument("--batch-threads", type=int, default=256)
+    ap.add_argument("--update-accepts", type=int, default=20_000)
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-iters", type=int, default=10**7)
+    ap.add_argument("--serve-slice", type=int, default=500_000)
+    ap.add_argument("--serve-slots", type=int, default=512)
+    ap.add_argument("--serve-budget", type=int, default=64 << 30)
+    ap.add_argument("--serve-time-limit", type=float, default=120.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(independent chains shard across GPUs without communication, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1208_2675_amd import qapsa as Q
+    from paper_1208_2675_amd import workloads as W
+
+    sections = set(args.sections.split(","))
+    s = section_single(Q, W, torch, args)
+    ch = s["ch"]
+    value = s["iters_total"] / s["wall"]
     line = {
         "metric": "SA iterations/s + Delta-updates/s, 1 GPU: single chain vs batched chains",
         "value": value,
@@ -109,24 +207,33 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": s["wall"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32 (Delta, costs int64, Eq. 2 in f64)",
+        "dtype": "int32 swap costs, int64 costs, Eq. 2 in f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: single chain, N={ch.n}, I={ch.iters:.0e}, "
                                f"geometric cooling T0=mean|Delta0| -> 1e-3*T0",
-                   "n": ch.n, "iters": ch.iters, "symmetric": sym, "instance_sha256": ch.meta["sha256"]},
-        "delta_updates_per_s": accepts_total / wall,
-        "acceptance_rate": int(st.accepts) / ch.iters,
-        "chain_kernel_ms": kernel_ms,
-        "parity_vs_oracle": parity,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_chain_lds (one workgroup, state in LDS)",
-                     "per_unit": f"{update_bytes(ch.n, sym)} B per accepted swap"},
+                   "n": ch.n, "iters": ch.iters, "symmetric": s["symmetric"], "instance_sha256": ch.meta["sha256"]},
+        "delta_updates_per_s": s["accepts_total"] / s["wall"],
+        "acceptance_rate": int(s["state"].accepts) / ch.iters,
+        "single_chain": {"kernel_ms": s["kernel_ms"], "parity_vs_oracle": s["parity"],
+                         "phase_cycles": s["phases"], "clock_hz": 2.4e9},
     }
+    if "batched" in sections:
+        b = section_batched(Q, W, torch, args)
+        b["ratio_vs_single_chain"] = b["value"] / value
+        line["batched"] = b
+    if "update" in sections:
+        u = section_update(Q, W, torch, args)
+        line["update_n2000"] = u
+        line["roofline"] = {"bound": "hbm", "achieved": u["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": u["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                            "kernel": "k_chain_dist (N=2000, every proposal accepted)",
+                            "per_unit": f"{u['bytes_per_update']} B per Delta update (int32 algorithmic)"}
+    if "serve" in sections:
+        line["serve"] = section_serve(Q, W, torch, args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ch, min(args.cpu_sample, ch.iters))
     print(json.dumps(line))

@@ -194,7 +194,9 @@ QAP_API int qap_delta_init(int32_t n, const int32_t* A, const int32_t* B, const 
                            qap_chain_state* state, hipStream_t stream);
 
 /* Bytes of device workspace a run of an n-facility instance may need
-   (qap_run_buffers.workspace); 64 + 16 n. */
+   (qap_run_buffers.workspace): the larger of the multi-workgroup exchange area
+   (64 + 16 n) and the one-workgroup scratch for asymmetric chains
+   (qap_chain_scratch_bytes(n, 0)). */
 QAP_API uint64_t qap_workspace_bytes(int32_t n);
 
 /* Number of doubles in the temperature table of a schedule of `iters` iterations:
@@ -263,6 +265,9 @@ typedef struct {
     uint64_t t_end;
     double T0;
     uint64_t seed;
+    void* scratch;              /* NULL, or qap_chain_scratch_bytes(n, symmetric) bytes of device
+                                   memory: the chain then keeps Delta in `delta` and byte copies
+                                   of A in scratch, and only B' uses LDS (larger n fits)       */
 } qap_chain_desc;
 
 typedef struct {
@@ -272,6 +277,15 @@ typedef struct {
                                    so one launch advances the whole batch by a slice            */
     uint64_t* phase_cycles;     /* optional QAP_PHASES counters summed over chains              */
 } qap_batch_config;
+
+/* 1 if one workgroup can hold a chain of n facilities whose A and B value
+   ranges (max - min) are a_range and b_range entirely in LDS; 2 if it can with
+   a per-chain scratch (qap_chain_desc.scratch); 0 otherwise. */
+QAP_API int qap_single_workgroup(int32_t n, int32_t symmetric, int64_t a_range, int64_t b_range);
+
+/* Bytes of the per-chain scratch of qap_chain_desc.scratch (and of the
+   single-chain workspace when a chain needs it). */
+QAP_API uint64_t qap_chain_scratch_bytes(int32_t n, int32_t symmetric);
 
 /* Bytes of device workspace qap_sa_run_batch needs (64). */
 QAP_API uint64_t qap_batch_workspace_bytes(void);
@@ -287,7 +301,8 @@ QAP_API uint64_t qap_batch_workspace_bytes(void);
  *   order       optional device array of n_chains chain indices (queue order)
  *   workspace   qap_batch_workspace_bytes() bytes of device memory
  * Each chain must be one a single workgroup can hold (byte value ranges; n up
- * to about 155 asymmetric or 195 symmetric); otherwise QAP_E_UNSUPPORTED.
+ * to about 155 asymmetric or 195 symmetric in LDS, about 280 with a scratch,
+ * see qap_single_workgroup); otherwise QAP_E_UNSUPPORTED.
  * Chains in one batch must not share state, p, Bp or delta buffers.
  */
 QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,

@@ -29,6 +29,29 @@ int check_schedule(const qap_schedule* s)
 
 }  // namespace
 
+namespace qapsa {
+
+int side_stream(hipStream_t* side, hipEvent_t* fork, hipEvent_t* join)
+{
+    static hipStream_t streams[64];
+    static hipEvent_t forks[64], joins[64];
+    static bool made[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return QAP_E_DEVICE;
+    if (!made[dev]) {
+        if (hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) return QAP_E_DEVICE;
+        if (hipEventCreateWithFlags(&forks[dev], hipEventDisableTiming) != hipSuccess) return QAP_E_DEVICE;
+        if (hipEventCreateWithFlags(&joins[dev], hipEventDisableTiming) != hipSuccess) return QAP_E_DEVICE;
+        made[dev] = true;
+    }
+    *side = streams[dev];
+    *fork = forks[dev];
+    *join = joins[dev];
+    return QAP_OK;
+}
+
+}  // namespace qapsa
+
 extern "C" {
 
 QAP_API const char* qap_strerror(int status)
@@ -64,7 +87,17 @@ QAP_API int qap_delta_init(int32_t n, const int32_t* A, const int32_t* B, const 
 
 QAP_API uint64_t qap_temp_table_len(uint64_t iters) { return temp_table_len(iters); }
 
-QAP_API uint64_t qap_workspace_bytes(int32_t n) { return n < 0 ? 0 : (uint64_t)dist_ws_bytes(n); }
+QAP_API uint64_t qap_workspace_bytes(int32_t n)
+{
+    if (n < 2) return 0;
+    const size_t a = dist_ws_bytes(n), b = wg_scratch_bytes(n, false);
+    return a > b ? a : b;
+}
+
+QAP_API uint64_t qap_chain_scratch_bytes(int32_t n, int32_t symmetric)
+{
+    return n < 2 ? 0 : (uint64_t)wg_scratch_bytes(n, symmetric != 0);
+}
 
 QAP_API int qap_schedule_tables(uint64_t iters, double alpha, double* temps, hipStream_t stream)
 {
@@ -107,6 +140,12 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
     if (bytes_ok && lds_wg_bytes(n, sym) <= budget) {
         const int threads = n >= 48 ? 1024 : 256;
         return launch_chain_wg(a, sym, threads, stream);
+    }
+    // one workgroup with Delta and A in device memory: asymmetric chains too big for LDS
+    if (bytes_ok && !sym && lds_wg_bytes(n, sym, true) <= budget) {
+        if (!bufs->workspace || bufs->workspace_bytes < wg_scratch_bytes(n, sym)) return QAP_E_INVAL;
+        a.gscratch = bufs->workspace;
+        return launch_chain_wg(a, sym, 1024, stream);
     }
     // many workgroups, one cooperative launch: symmetric byte-valued instances
     if (bytes_ok && sym) {
@@ -152,6 +191,15 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
 
 QAP_API uint64_t qap_batch_workspace_bytes(void) { return sizeof(BatchWs); }
 
+QAP_API int qap_single_workgroup(int32_t n, int32_t symmetric, int64_t a_range, int64_t b_range)
+{
+    if (n < 2 || a_range < 0 || b_range < 0 || a_range > 255 || b_range > 255) return 0;
+    const size_t budget = kLdsLimit - kLdsStaticReserve;
+    if (lds_wg_bytes(n, symmetric != 0) <= budget) return 1;
+    if (lds_wg_bytes(n, symmetric != 0, true) <= budget) return 2;
+    return 0;
+}
+
 QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs, const qap_chain_desc* dev_descs,
                              const int32_t* order, const qap_batch_config* cfg, void* workspace,
                              hipStream_t stream)
@@ -160,7 +208,8 @@ QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,
     if (n_chains == 0) return QAP_OK;
     const int threads = cfg->threads ? cfg->threads : 256;
     if (threads < 64 || threads > 256 || threads % 64) return QAP_E_INVAL;
-    size_t lds = 0;
+    size_t lds = 0, lds_g = 0;
+    int kinds[2] = {0, 0};
     for (int i = 0; i < n_chains; ++i) {
         const qap_chain_desc& d = host_descs[i];
         if (d.n < 2 || d.n > 46340 || !d.A || !d.Bp || !d.p || !d.delta || !d.state || !d.temps) return QAP_E_INVAL;
@@ -168,23 +217,13 @@ QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,
         if ((d.flags & ~(QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY)) != 0 || d.switch_permille > 1000)
             return QAP_E_INVAL;
         if ((int64_t)d.a_max - d.a_min > 255 || (int64_t)d.b_max - d.b_min > 255) return QAP_E_UNSUPPORTED;
-        const size_t b = lds_wg_bytes(d.n, d.symmetric != 0);
+        const bool g = d.scratch != nullptr;
+        const size_t b = lds_wg_bytes(d.n, d.symmetric != 0, g);
         if (b > kLdsLimit - kLdsStaticReserve) return QAP_E_UNSUPPORTED;
-        if (b > lds) lds = b;
+        size_t& slot = g ? lds_g : lds;
+        if (b > slot) slot = b;
+        kinds[g ? 1 : 0] += 1;
     }
-    int groups = cfg->groups;
-    if (groups <= 0) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            return QAP_E_DEVICE;
-        const size_t per_cu_lds = (kLdsLimit) / (lds + kLdsStaticReserve);
-        const size_t per_cu_waves = 32 / (threads / 64);   // 8 waves per SIMD
-        size_t per_cu = per_cu_lds < per_cu_waves ? per_cu_lds : per_cu_waves;
-        if (per_cu < 1) per_cu = 1;
-        groups = (int)((size_t)cus * per_cu);
-    }
-    if (groups > n_chains) groups = n_chains;
     BatchArgs b{};
     b.n_chains = n_chains;
     b.descs = dev_descs;
@@ -192,7 +231,7 @@ QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,
     b.ws = (BatchWs*)workspace;
     b.slice = cfg->slice;
     b.prof = cfg->phase_cycles;
-    return launch_chain_batch(b, groups, threads, lds, stream);
+    return launch_chain_batch(b, cfg->groups, kinds[0], kinds[1], threads, lds, lds_g, stream);
 }
 
 }  // extern "C"

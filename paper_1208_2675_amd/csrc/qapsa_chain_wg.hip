@@ -69,16 +69,20 @@ struct Wg {
 
 __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-__host__ __device__ inline size_t wg_layout(int n, int q, bool sym, char* base, Wg* L)
+// LDS layout of one chain.  With `gbase` (global scratch of wg_global_bytes)
+// the read-only byte copies of A and A^T live there and Delta stays in the
+// caller's buffer `gdelta`, so only B', B'^T and small vectors use LDS.
+__host__ __device__ inline size_t wg_layout(int n, int q, bool sym, char* base, Wg* L,
+                                           char* gbase = nullptr, int32_t* gdelta = nullptr, bool gmem = false)
 {
     const size_t m = (size_t)n * (n - 1) / 2, P = 4 * (size_t)q;
     size_t off = 0;
     auto take = [&](size_t bytes) { char* p = base ? base + off : nullptr; off = a16(off + bytes); return p; };
-    char* ab = take(n * P);
-    char* at = sym ? nullptr : take(n * P);
+    char* ab = gmem ? gbase : take(n * P);
+    char* at = sym ? nullptr : (gmem ? (gbase ? gbase + n * P : nullptr) : take(n * P));
     char* bb = take(n * P);
     char* bt = sym ? nullptr : take(n * P);
-    char* d = take(4 * m);
+    char* d = gmem ? (char*)gdelta : take(4 * m);
     char* abp = take(4 * (size_t)n);
     char* bbp = take(4 * (size_t)n);
     char* tu = take(4 * (size_t)n);
@@ -162,7 +166,9 @@ __device__ __forceinline__ void advance_pair(int n, int& r, int& s, int k)
     }
 }
 
-template <bool SYM>
+inline size_t wg_global_bytes(int n, int q, bool sym) { return (sym ? 1 : 2) * (size_t)n * 4 * q; }
+
+template <bool SYM, bool GMEM>
 struct Chain {
     const ChainArgs& a;
     Wg L;
@@ -178,7 +184,7 @@ struct Chain {
         m = (uint32_t)((int64_t)n * (n - 1) / 2);
         tid = threadIdx.x; nt = blockDim.x;
         lane = tid & 63; wave = uni(tid >> 6); nwaves = nt >> 6;
-        wg_layout(n, q, SYM, smem, &L);
+        wg_layout(n, q, SYM, smem, &L, (char*)a.gscratch, a.delta, GMEM);
     }
 
     __device__ __forceinline__ int Ae(int i, int j) const { return L.Ab[i * P + j]; }
@@ -330,7 +336,7 @@ struct Chain {
     }
 };
 
-template <bool SYM>
+template <bool SYM, bool GMEM>
 __device__ void chain_run(const ChainArgs& a, char* smem)
 {
     // Cross-wave exchange only; the chain's scalars live in registers of every
@@ -342,7 +348,7 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
     __shared__ int s_self[2];
     __shared__ unsigned long long s_prof[QAP_PHASES];
 
-    Chain<SYM> C(a, smem);
+    Chain<SYM, GMEM> C(a, smem);
     const Wg& L = C.L;
     const int n = C.n, P = C.P, tid = C.tid, nt = C.nt, lane = C.lane, wave = C.wave, nwaves = C.nwaves;
     const uint32_t m = C.m;
@@ -388,7 +394,7 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
         return;
     }
     int mode = (a.flags & kFlagDeltaOnly) ? 1 : (a.flags & kFlagScratchOnly) ? 0 : st0.mode;
-    if (mode == 1) {   // the caller's Delta is valid for p after qap_delta_init and after every run
+    if (mode == 1 && !GMEM) {   // the caller's Delta is valid for p after qap_delta_init and after every run
         for (uint32_t i = tid; i < m; i += nt) L.D[i] = a.delta[i];
         __syncthreads();
     }
@@ -698,7 +704,8 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
     if (mode == 0) C.build_delta(s_self);   // the caller's Delta stays valid in either mode
     __syncthreads();
     if (tid == 0) mark(QAP_PH_BUILD);
-    for (uint32_t i = tid; i < m; i += nt) a.delta[i] = L.D[i];
+    if (!GMEM)
+        for (uint32_t i = tid; i < m; i += nt) a.delta[i] = L.D[i];
     for (int e = tid; e < n * n; e += nt) {
         const int i = e / n, j = e - i * n;
         a.Bp[e] = (int32_t)L.Bb[i * P + j] + a.b_min;
@@ -720,28 +727,34 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
     }
 }
 
-template <bool SYM>
+template <bool SYM, bool GMEM>
 __global__ void __launch_bounds__(1024) k_chain_wg(ChainArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    chain_run<SYM>(a, smem);
+    chain_run<SYM, GMEM>(a, smem);
 }
 
 // Many independent chains in one persistent launch: each workgroup takes the
 // next chain from a device-wide queue and runs it (or its next slice) with the
-// one-workgroup routine above.
+// one-workgroup routine above.  One instantiation serves the chains whose
+// state is all in LDS, the other those that keep Delta and A in device memory
+// (a per-chain scratch); each skips the other kind, so both can walk the same
+// descriptor array concurrently.
+template <bool GMEM>
 __global__ void __launch_bounds__(256) k_chain_batch(BatchArgs b)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_idx;
+    unsigned* next = &b.ws->next[GMEM ? 1 : 0];
     for (;;) {
-        if (threadIdx.x == 0) s_idx = (int)atomicAdd(&b.ws->next, 1u);
+        if (threadIdx.x == 0) s_idx = (int)atomicAdd(next, 1u);
         __syncthreads();
         const int idx = s_idx;
         __syncthreads();
         if (idx >= b.n_chains) break;
         const int c = b.order ? b.order[idx] : idx;
         const qap_chain_desc d = b.descs[c];
+        if ((d.scratch != nullptr) != GMEM) continue;
         ChainArgs a{};
         a.n = d.n;
         a.quads = ((d.n + 3) / 4) | 1;
@@ -761,25 +774,68 @@ __global__ void __launch_bounds__(256) k_chain_batch(BatchArgs b)
         a.T0 = d.T0;
         a.seed = d.seed;
         a.chain_id = d.chain_id;
-        if (d.symmetric) chain_run<true>(a, smem);
-        else chain_run<false>(a, smem);
+        a.gscratch = d.scratch;
+        if (d.symmetric) chain_run<true, GMEM>(a, smem);
+        else chain_run<false, GMEM>(a, smem);
         __syncthreads();
     }
 }
 
-__global__ void k_batch_reset(BatchWs* ws) { ws->next = 0; }
+__global__ void k_batch_reset(BatchWs* ws) { ws->next[0] = 0; ws->next[1] = 0; }
 
 }  // namespace
 
-int launch_chain_batch(const BatchArgs& b, int groups, int threads, size_t lds_bytes, hipStream_t stream)
+int launch_chain_batch(const BatchArgs& b, int groups, int count_lds, int count_gmem, int threads,
+                       size_t lds_bytes, size_t gmem_lds_bytes, hipStream_t stream)
 {
-    const void* fn = (const void*)k_chain_batch;
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess)
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return QAP_E_DEVICE;
+    auto size = [&](const void* fn, size_t bytes, int count, int* out) -> int {
+        *out = 0;
+        if (count == 0) return QAP_OK;
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+            return QAP_E_DEVICE;
+        int g = groups;
+        if (g <= 0) {
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, bytes) != hipSuccess)
+                return QAP_E_DEVICE;
+            g = (per_cu < 1 ? 1 : per_cu) * cus;
+        }
+        *out = g > count ? count : g;
+        return QAP_OK;
+    };
+    int groups_lds = 0, groups_gmem = 0;
+    if (size((const void*)k_chain_batch<false>, lds_bytes, count_lds, &groups_lds) != QAP_OK ||
+        size((const void*)k_chain_batch<true>, gmem_lds_bytes, count_gmem, &groups_gmem) != QAP_OK)
         return QAP_E_DEVICE;
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, stream, b.ws);
     BatchArgs args = b;
     void* kargs[] = {&args};
-    if (hipLaunchKernel(fn, dim3(groups), dim3(threads), kargs, lds_bytes, stream) != hipSuccess)
+    if (groups_lds > 0 && groups_gmem > 0) {
+        // the two kinds run side by side: fork onto a second stream, join back
+        hipStream_t side;
+        hipEvent_t fork, join;
+        if (side_stream(&side, &fork, &join) != QAP_OK) return QAP_E_DEVICE;
+        if (hipEventRecord(fork, stream) != hipSuccess || hipStreamWaitEvent(side, fork, 0) != hipSuccess)
+            return QAP_E_DEVICE;
+        if (hipLaunchKernel((const void*)k_chain_batch<true>, dim3(groups_gmem), dim3(threads), kargs,
+                            gmem_lds_bytes, side) != hipSuccess)
+            return QAP_E_DEVICE;
+        if (hipLaunchKernel((const void*)k_chain_batch<false>, dim3(groups_lds), dim3(threads), kargs, lds_bytes,
+                            stream) != hipSuccess)
+            return QAP_E_DEVICE;
+        if (hipEventRecord(join, side) != hipSuccess || hipStreamWaitEvent(stream, join, 0) != hipSuccess)
+            return QAP_E_DEVICE;
+        return QAP_OK;
+    }
+    if (groups_lds > 0 && hipLaunchKernel((const void*)k_chain_batch<false>, dim3(groups_lds), dim3(threads), kargs,
+                                          lds_bytes, stream) != hipSuccess)
+        return QAP_E_DEVICE;
+    if (groups_gmem > 0 && hipLaunchKernel((const void*)k_chain_batch<true>, dim3(groups_gmem), dim3(threads), kargs,
+                                           gmem_lds_bytes, stream) != hipSuccess)
         return QAP_E_DEVICE;
     return QAP_OK;
 }
@@ -789,15 +845,19 @@ int wg_quads(int n)
     return ((n + 3) / 4) | 1;   // odd dword pitch: strided row reads hit distinct banks
 }
 
-size_t lds_wg_bytes(int n, bool symmetric)
+size_t lds_wg_bytes(int n, bool symmetric, bool gmem)
 {
-    return wg_layout(n, wg_quads(n), symmetric, nullptr, nullptr);
+    return wg_layout(n, wg_quads(n), symmetric, nullptr, nullptr, nullptr, nullptr, gmem);
 }
+
+size_t wg_scratch_bytes(int n, bool symmetric) { return wg_global_bytes(n, wg_quads(n), symmetric); }
 
 int launch_chain_wg(const ChainArgs& a, bool symmetric, int threads, hipStream_t stream)
 {
-    const size_t bytes = lds_wg_bytes(a.n, symmetric);
-    const void* fn = symmetric ? (const void*)k_chain_wg<true> : (const void*)k_chain_wg<false>;
+    const bool gmem = a.gscratch != nullptr;
+    const size_t bytes = lds_wg_bytes(a.n, symmetric, gmem);
+    const void* fn = symmetric ? (gmem ? (const void*)k_chain_wg<true, true> : (const void*)k_chain_wg<true, false>)
+                               : (gmem ? (const void*)k_chain_wg<false, true> : (const void*)k_chain_wg<false, false>);
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
         return QAP_E_DEVICE;
     ChainArgs args = a;

@@ -36,6 +36,7 @@ struct ChainArgs {
     int64_t* acc_log;
     uint64_t acc_cap;
     uint64_t* prof;       // optional phase counters (QAP_PHASES)
+    void* gscratch;       // byte kernel: global scratch for A and A^T bytes (Delta stays in `delta`)
     uint64_t iters;
     uint64_t t_end;
     double T0;
@@ -103,8 +104,8 @@ int launch_chain_dist(const DistArgs& a, int G, int threads, hipStream_t stream)
 
 // batched chains (one persistent launch, a device-wide work queue)
 struct BatchWs {
-    unsigned next;
-    unsigned pad[15];
+    unsigned next[2];   // queue positions of the LDS-resident and the scratch-backed kernel
+    unsigned pad[14];
 };
 struct BatchArgs {
     int32_t n_chains;
@@ -115,11 +116,17 @@ struct BatchArgs {
     uint64_t slice;
     uint64_t* prof;
 };
-int launch_chain_batch(const BatchArgs& b, int groups, int threads, size_t lds_bytes, hipStream_t stream);
+// groups <= 0: as many workgroups as can be resident at once (occupancy of each
+// kernel at its LDS size times the CU count), never more than its chains
+int launch_chain_batch(const BatchArgs& b, int groups, int count_lds, int count_gmem, int threads,
+                       size_t lds_bytes, size_t gmem_lds_bytes, hipStream_t stream);
+// a second stream (default priority) and two events of the current device, created once
+int side_stream(hipStream_t* side, hipEvent_t* fork, hipEvent_t* join);
 
 // byte-valued chain kernel (scratch and Delta modes)
 int wg_quads(int n);
-size_t lds_wg_bytes(int n, bool symmetric);
+size_t lds_wg_bytes(int n, bool symmetric, bool gmem = false);
+size_t wg_scratch_bytes(int n, bool symmetric);
 int launch_chain_wg(const ChainArgs& a, bool symmetric, int threads, hipStream_t stream);
 
 }  // namespace qapsa

@@ -264,7 +264,7 @@ class ChainDesc(C.Structure):
                 ("A", C.c_void_p), ("Bp", C.c_void_p), ("p", C.c_void_p), ("delta", C.c_void_p),
                 ("state", C.c_void_p), ("temps", C.c_void_p), ("ties", C.c_void_p), ("tie_cap", C.c_uint32),
                 ("chain_id", C.c_uint32), ("iters", C.c_uint64), ("t_end", C.c_uint64), ("T0", C.c_double),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("scratch", C.c_void_p)]
 
 
 class BatchConfig(C.Structure):
@@ -277,6 +277,31 @@ _lib.qap_batch_workspace_bytes.restype = C.c_uint64
 _lib.qap_sa_run_batch.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(BatchConfig),
                                   C.c_void_p, C.c_void_p]
 _lib.qap_sa_run_batch.restype = C.c_int
+
+
+_lib.qap_single_workgroup.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.c_int64]
+_lib.qap_single_workgroup.restype = C.c_int
+
+
+def qap_single_workgroup(n: int, symmetric: int, a_range: int, b_range: int) -> int:
+    return int(_lib.qap_single_workgroup(n, symmetric, a_range, b_range))
+
+
+def fits_one_workgroup(n: int, symmetric: bool, a_range: int, b_range: int) -> bool:
+    """True if one workgroup can hold the chain (in LDS, or with a per-chain scratch)."""
+    return qap_single_workgroup(n, int(symmetric), a_range, b_range) != 0
+
+
+def needs_scratch(n: int, symmetric: bool, a_range: int, b_range: int) -> bool:
+    return qap_single_workgroup(n, int(symmetric), a_range, b_range) == 2
+
+
+_lib.qap_chain_scratch_bytes.argtypes = [C.c_int32, C.c_int32]
+_lib.qap_chain_scratch_bytes.restype = C.c_uint64
+
+
+def qap_chain_scratch_bytes(n: int, symmetric: int) -> int:
+    return int(_lib.qap_chain_scratch_bytes(n, symmetric))
 
 
 def qap_batch_workspace_bytes() -> int:
@@ -329,6 +354,7 @@ class Batch:
             po += ch.n; bo += ch.n * ch.n; do += max(ch.n * (ch.n - 1) // 2, 1); to += qap_temp_table_len(ch.iters)
         self.p.copy_(torch.from_numpy(np.concatenate([np.asarray(ch.p0, dtype=np.int32) for ch in chains])).to(dev))
         self.descs = None
+        self.scratch = {}
 
     def init(self, ratio: float = 1e-3, flags: int = 0, switch_permille: int = 0):
         torch = self.torch
@@ -354,11 +380,16 @@ class Batch:
             temps = self.temps.data_ptr() + f8 * to
             _check(qap_schedule_tables(ch.iters, alpha, temps), "qap_schedule_tables")
             A, _ = self.views[i]
+            scr = None
+            if needs_scratch(ch.n, bool(inf.symmetric), inf.a_max - inf.a_min, inf.b_max - inf.b_min):
+                self.scratch[i] = torch.empty(qap_chain_scratch_bytes(ch.n, inf.symmetric), dtype=torch.uint8,
+                                              device=self.p.device)
+                scr = self.scratch[i].data_ptr()
             descs[i] = ChainDesc(ch.n, inf.symmetric, inf.a_min, inf.a_max, inf.b_min, inf.b_max, flags,
                                  switch_permille, A.data_ptr(), self.Bp.data_ptr() + i4 * bo,
                                  self.p.data_ptr() + i4 * po, self.delta.data_ptr() + i4 * do,
                                  self.state_d[i].data_ptr(), temps, self.ties[i].data_ptr(), self.tie_cap,
-                                 ch.chain_id, ch.iters, ch.iters, T0, ch.philox_seed & (2**64 - 1))
+                                 ch.chain_id, ch.iters, ch.iters, T0, ch.philox_seed & (2**64 - 1), scr)
         self.descs = descs
         raw = np.frombuffer(bytes(descs), dtype=np.uint8).copy()
         self.descs_d = torch.from_numpy(raw).to(self.p.device)

@@ -62,7 +62,13 @@ def test_host_side_argument_errors(qlib):
     assert Q.qap_strerror(Q.QAP_E_RANGE).startswith("instance values")
     assert Q.qap_temp_table_len(10**9) == 2048 + 954
     assert Q.qap_temp_table_len(1) == 2049
-    assert Q.qap_workspace_bytes(2000) == 64 + 16 * 2000
+    q = lambda n: (((n + 3) // 4) | 1) * 4
+    for n in (2, 150, 2000):
+        assert Q.qap_workspace_bytes(n) == max(64 + 16 * n, 2 * n * q(n))
+    assert Q.qap_single_workgroup(150, 0, 99, 23) == 1 and Q.qap_single_workgroup(195, 1, 99, 99) == 1
+    assert Q.qap_single_workgroup(200, 0, 99, 27) == 2 and Q.qap_single_workgroup(2000, 1, 99, 141) == 0
+    assert Q.qap_chain_scratch_bytes(200, 0) == 2 * 200 * 204
+    assert Q.qap_single_workgroup(100, 1, 300, 9) == 0
     fake = 0x1000  # never dereferenced: every call below is rejected first
     assert Q.qap_sa_run(8, fake, None, fake, fake, fake, fake, Q.Schedule(100, 100, 1.0, 0.99, 1, 0, 0, 0, 0),
                         Q.InstanceInfo(0, 0, 0, 9, 0, 9, 1, 0), Q.RunBuffers(fake, None, 0, 0, None, 0), 0) == Q.QAP_E_INVAL
