@@ -92,12 +92,16 @@ typedef struct {
     int32_t status;      /* QAP_OK, or the first error the device saw                 */
     int32_t mode;        /* how swap costs are produced: QAP_MODE_SCRATCH (each proposal's
                             cost computed in O(N) when it is met) or QAP_MODE_DELTA (the
-                            Delta matrix of Sec. 2.2 is kept); the caller's delta buffer
-                            holds Delta for the current p in both modes                 */
+                            Delta matrix of Sec. 2.2 is kept), and whether the caller's
+                            delta buffer holds Delta for the current p: it does in
+                            QAP_MODE_SCRATCH and QAP_MODE_DELTA; QAP_MODE_SCRATCH_STALE
+                            (scratch mode, delta left as it was) follows a call that
+                            stopped in scratch mode before t = iters                   */
 } qap_chain_state;
 
 #define QAP_MODE_SCRATCH 0
 #define QAP_MODE_DELTA 1
+#define QAP_MODE_SCRATCH_STALE 2
 
 /* One near tie of Eq. (2). */
 typedef struct {
@@ -114,7 +118,7 @@ typedef struct {
     double alpha;        /* per-iteration cooling factor, 0 < alpha <= 1              */
     uint64_t seed;       /* generator key                                             */
     uint32_t chain_id;   /* third generator counter word                              */
-    uint32_t flags;      /* 0, QAP_FLAG_DELTA_ONLY or QAP_FLAG_SCRATCH_ONLY           */
+    uint32_t flags;      /* 0 or QAP_FLAG_* below                                      */
     uint32_t switch_permille; /* a chain in scratch mode moves to Delta mode when fewer
                             than this many proposals per 1000 were accepted over the
                             last 8192 iterations; 0 selects the default (20)          */
@@ -125,6 +129,9 @@ typedef struct {
    costs; the flags only pin the mode. */
 #define QAP_FLAG_DELTA_ONLY 1u    /* keep the Delta matrix from the first iteration (Sec. 2.2) */
 #define QAP_FLAG_SCRATCH_ONLY 2u  /* never build the Delta matrix during the run              */
+#define QAP_FLAG_MULTI_WG 4u      /* symmetric byte-valued instances: run on the multi-workgroup
+                                     kernel even where one workgroup could hold the chain
+                                     (qap_sa_run only; the result is the same)                */
 
 /* Device buffers a run reads or appends to (host struct of device pointers). */
 typedef struct {
@@ -161,7 +168,7 @@ enum {
     QAP_PH_N_THRESH = 12,      /* threshold refills                                */
     QAP_PH_SWITCH_T = 13,      /* iteration at which the chain entered Delta mode  */
     QAP_PH_N_SCANNED = 14,     /* proposals tested in Delta mode                   */
-    QAP_PH_RESERVED = 15,
+    QAP_PH_GRID_SYNC = 15,     /* cycles from a scan window to the grid-wide result (multi-workgroup) */
     QAP_PHASES = 16
 };
 
@@ -195,7 +202,7 @@ QAP_API int qap_delta_init(int32_t n, const int32_t* A, const int32_t* B, const 
 
 /* Bytes of device workspace a run of an n-facility instance may need
    (qap_run_buffers.workspace): the larger of the multi-workgroup exchange area
-   (64 + 16 n) and the one-workgroup scratch for asymmetric chains
+   (16448 + 16 n) and the one-workgroup scratch for asymmetric chains
    (qap_chain_scratch_bytes(n, 0)). */
 QAP_API uint64_t qap_workspace_bytes(int32_t n);
 
@@ -227,8 +234,11 @@ QAP_API int qap_schedule_tables(uint64_t iters, double alpha, double* temps, hip
  * In QAP_MODE_DELTA it also updates every Delta entry: pairs disjoint from
  * {u, v} by an O(1) correction, pairs that meet {u, v} by an O(n)
  * recomputation (the general asymmetric form).  In QAP_MODE_SCRATCH each
- * proposal's swap cost is computed in O(n) when it is met, and Delta is rebuilt
- * at the end of the call.  The run is identical whatever the split of
+ * proposal's swap cost is computed in O(n) when it is met; Delta is rebuilt
+ * when the chain moves to Delta mode and when a call ends the schedule
+ * (t = iters), and is otherwise left stale (state->mode says which).  The
+ * multi-workgroup and 16-bit kernels need a current Delta and fail with
+ * QAP_E_STATE on a stale one.  The run is identical whatever the split of
  * [0, iters) into calls and whichever mode is active.
  * Kernels: one workgroup holds the chain when its matrices fit one CU's LDS;
  * otherwise (symmetric instances up to a few thousand facilities) the chain

@@ -21,7 +21,7 @@ int check_schedule(const qap_schedule* s)
     if (s->iters == 0 || s->t_end > s->iters) return QAP_E_INVAL;
     if (!(s->T0 > 0.0)) return QAP_E_INVAL;                // rejects NaN and <= 0; +inf allowed
     if (!(s->alpha > 0.0) || s->alpha > 1.0) return QAP_E_INVAL;
-    if ((s->flags & ~(QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY)) != 0) return QAP_E_INVAL;
+    if ((s->flags & ~(QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY | QAP_FLAG_MULTI_WG)) != 0) return QAP_E_INVAL;
     if ((s->flags & QAP_FLAG_DELTA_ONLY) && (s->flags & QAP_FLAG_SCRATCH_ONLY)) return QAP_E_INVAL;
     if (s->switch_permille > 1000 || s->reserved != 0) return QAP_E_INVAL;
     return QAP_OK;
@@ -31,22 +31,23 @@ int check_schedule(const qap_schedule* s)
 
 namespace qapsa {
 
-int side_stream(hipStream_t* side, hipEvent_t* fork, hipEvent_t* join)
+int side_stream(int which, hipStream_t* side, hipEvent_t* fork, hipEvent_t* join)
 {
-    static hipStream_t streams[64];
-    static hipEvent_t forks[64], joins[64];
-    static bool made[64];
+    static hipStream_t streams[64][3];
+    static hipEvent_t forks[64][3], joins[64][3];
+    static bool made[64][3];
     int dev = 0;
+    if (which < 0 || which > 2) return QAP_E_INVAL;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return QAP_E_DEVICE;
-    if (!made[dev]) {
-        if (hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) return QAP_E_DEVICE;
-        if (hipEventCreateWithFlags(&forks[dev], hipEventDisableTiming) != hipSuccess) return QAP_E_DEVICE;
-        if (hipEventCreateWithFlags(&joins[dev], hipEventDisableTiming) != hipSuccess) return QAP_E_DEVICE;
-        made[dev] = true;
+    if (!made[dev][which]) {
+        if (hipStreamCreateWithFlags(&streams[dev][which], hipStreamNonBlocking) != hipSuccess) return QAP_E_DEVICE;
+        if (hipEventCreateWithFlags(&forks[dev][which], hipEventDisableTiming) != hipSuccess) return QAP_E_DEVICE;
+        if (hipEventCreateWithFlags(&joins[dev][which], hipEventDisableTiming) != hipSuccess) return QAP_E_DEVICE;
+        made[dev][which] = true;
     }
-    *side = streams[dev];
-    *fork = forks[dev];
-    *join = joins[dev];
+    *side = streams[dev][which];
+    *fork = forks[dev][which];
+    *join = joins[dev][which];
     return QAP_OK;
 }
 
@@ -90,13 +91,22 @@ QAP_API uint64_t qap_temp_table_len(uint64_t iters) { return temp_table_len(iter
 QAP_API uint64_t qap_workspace_bytes(int32_t n)
 {
     if (n < 2) return 0;
-    const size_t a = dist_ws_bytes(n), b = wg_scratch_bytes(n, false);
-    return a > b ? a : b;
+    size_t bytes = dist_ws_bytes(n);
+    for (int sym = 0; sym < 2; ++sym) {
+        const int place = wg_place(n, sym != 0);
+        if (place >= 0) {
+            const size_t b = wg_scratch_bytes(n, sym != 0, place);
+            if (b > bytes) bytes = b;
+        }
+    }
+    return bytes;
 }
 
 QAP_API uint64_t qap_chain_scratch_bytes(int32_t n, int32_t symmetric)
 {
-    return n < 2 ? 0 : (uint64_t)wg_scratch_bytes(n, symmetric != 0);
+    if (n < 2) return 0;
+    const int place = wg_place(n, symmetric != 0);
+    return place < 0 ? 0 : (uint64_t)wg_scratch_bytes(n, symmetric != 0, place);
 }
 
 QAP_API int qap_schedule_tables(uint64_t iters, double alpha, double* temps, hipStream_t stream)
@@ -137,15 +147,16 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
 
     // byte-valued kernel: value ranges of A and B fit 0..255 after shifting
     const bool bytes_ok = (int64_t)info->a_max - info->a_min <= 255 && (int64_t)info->b_max - info->b_min <= 255;
-    if (bytes_ok && lds_wg_bytes(n, sym) <= budget) {
-        const int threads = n >= 48 ? 1024 : 256;
-        return launch_chain_wg(a, sym, threads, stream);
-    }
-    // one workgroup with Delta and A in device memory: asymmetric chains too big for LDS
-    if (bytes_ok && !sym && lds_wg_bytes(n, sym, true) <= budget) {
-        if (!bufs->workspace || bufs->workspace_bytes < wg_scratch_bytes(n, sym)) return QAP_E_INVAL;
+    const bool multi = (sched->flags & QAP_FLAG_MULTI_WG) != 0 && sym;
+    a.flags &= ~QAP_FLAG_MULTI_WG;
+    int place = bytes_ok && !multi ? wg_place(n, sym) : -1;
+    if (sym && place == 3) place = -1;   // large symmetric chains: many workgroups share the Delta update
+    // one workgroup: Delta, then A, then B' in device memory where LDS runs out
+    if (place >= 0 && place <= 1) return launch_chain_wg(a, sym, place, stream);
+    if (place >= 2) {
+        if (!bufs->workspace || bufs->workspace_bytes < wg_scratch_bytes(n, sym, place)) return QAP_E_INVAL;
         a.gscratch = bufs->workspace;
-        return launch_chain_wg(a, sym, 1024, stream);
+        return launch_chain_wg(a, sym, place, stream);
     }
     // many workgroups, one cooperative launch: symmetric byte-valued instances
     if (bytes_ok && sym) {
@@ -164,7 +175,7 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
             d.a_min = info->a_min;
             d.b_min = info->b_min;
             d.kmin = 4096;
-            d.kmax = 1u << 22;
+            d.kmax = (1u << 22) - 2;   // window offsets fit the 22-bit field of an exchange slot
             d.spin_limit = 1ull << 22;
             d.A = A; d.B = B; d.Bp = Bp; d.p = p; d.delta = delta; d.state = state;
             d.temps = bufs->temps;
@@ -174,7 +185,8 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
             d.iters = sched->iters; d.t_end = sched->t_end; d.T0 = sched->T0;
             d.seed = sched->seed; d.chain_id = sched->chain_id;
             d.ws = (DistWs*)bufs->workspace;
-            d.X = (int*)((char*)bufs->workspace + sizeof(DistWs));
+            d.slots = dist_slots(bufs->workspace);
+            d.X = dist_X(bufs->workspace);
             return launch_chain_dist(d, G, 512, stream);
         }
     }
@@ -194,9 +206,9 @@ QAP_API uint64_t qap_batch_workspace_bytes(void) { return sizeof(BatchWs); }
 QAP_API int qap_single_workgroup(int32_t n, int32_t symmetric, int64_t a_range, int64_t b_range)
 {
     if (n < 2 || a_range < 0 || b_range < 0 || a_range > 255 || b_range > 255) return 0;
-    const size_t budget = kLdsLimit - kLdsStaticReserve;
-    if (lds_wg_bytes(n, symmetric != 0) <= budget) return 1;
-    if (lds_wg_bytes(n, symmetric != 0, true) <= budget) return 2;
+    const int place = wg_place(n, symmetric != 0);
+    if (place == 0 || place == 1) return 1;
+    if (place >= 2) return 2;
     return 0;
 }
 
@@ -207,9 +219,9 @@ QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,
     if (n_chains < 0 || (n_chains > 0 && (!host_descs || !dev_descs)) || !cfg || !workspace) return QAP_E_INVAL;
     if (n_chains == 0) return QAP_OK;
     const int threads = cfg->threads ? cfg->threads : 256;
-    if (threads < 64 || threads > 256 || threads % 64) return QAP_E_INVAL;
-    size_t lds = 0, lds_g = 0;
-    int kinds[2] = {0, 0};
+    if (threads != 256) return QAP_E_INVAL;
+    size_t lds[4] = {0, 0, 0, 0};
+    int kinds[4] = {0, 0, 0, 0};
     for (int i = 0; i < n_chains; ++i) {
         const qap_chain_desc& d = host_descs[i];
         if (d.n < 2 || d.n > 46340 || !d.A || !d.Bp || !d.p || !d.delta || !d.state || !d.temps) return QAP_E_INVAL;
@@ -217,12 +229,12 @@ QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,
         if ((d.flags & ~(QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY)) != 0 || d.switch_permille > 1000)
             return QAP_E_INVAL;
         if ((int64_t)d.a_max - d.a_min > 255 || (int64_t)d.b_max - d.b_min > 255) return QAP_E_UNSUPPORTED;
-        const bool g = d.scratch != nullptr;
-        const size_t b = lds_wg_bytes(d.n, d.symmetric != 0, g);
-        if (b > kLdsLimit - kLdsStaticReserve) return QAP_E_UNSUPPORTED;
-        size_t& slot = g ? lds_g : lds;
-        if (b > slot) slot = b;
-        kinds[g ? 1 : 0] += 1;
+        const int place = wg_place(d.n, d.symmetric != 0);
+        if (place < 0) return QAP_E_UNSUPPORTED;
+        if (place >= 2 && !d.scratch) return QAP_E_INVAL;
+        const size_t b = lds_wg_bytes(d.n, d.symmetric != 0, place);
+        if (b > lds[place]) lds[place] = b;
+        kinds[place] += 1;
     }
     BatchArgs b{};
     b.n_chains = n_chains;
@@ -231,7 +243,7 @@ QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,
     b.ws = (BatchWs*)workspace;
     b.slice = cfg->slice;
     b.prof = cfg->phase_cycles;
-    return launch_chain_batch(b, cfg->groups, kinds[0], kinds[1], threads, lds, lds_g, stream);
+    return launch_chain_batch(b, cfg->groups, kinds, threads, lds, stream);
 }
 
 }  // extern "C"

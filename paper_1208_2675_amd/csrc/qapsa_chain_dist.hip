@@ -129,16 +129,59 @@ struct Rec {
     int32_t d;
 };
 
-__global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
+// Exchange slots: bits 63..54 the window number (mod 1024), 53..32 the window
+// offset j of the workgroup's first acceptance, 31..0 its Delta; a workgroup
+// without acceptance publishes all ones in bits 53..0.  The minimum over slots of the
+// low 54 bits is the window's first acceptance.
+constexpr unsigned long long kKeyBits = (1ull << 54) - 1;
+constexpr unsigned long long kNone = kKeyBits;
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned long long dpp_min_step(unsigned long long v)
+{
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0xffffffffu, (uint32_t)v, CTRL, ROW_MASK, 0xf, false);
+    const uint32_t hi = __builtin_amdgcn_update_dpp(0xffffffffu, (uint32_t)(v >> 32), CTRL, ROW_MASK, 0xf, false);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+    return o < v ? o : v;
+}
+
+// Minimum over the 64 lanes (DPP row shifts and broadcasts; lanes that read
+// outside their row see the identity), returned to every lane from lane 63.
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
+{
+    v = dpp_min_step<0x111, 0xf>(v);
+    v = dpp_min_step<0x112, 0xf>(v);
+    v = dpp_min_step<0x114, 0xf>(v);
+    v = dpp_min_step<0x118, 0xf>(v);
+    v = dpp_min_step<0x142, 0xa>(v);
+    v = dpp_min_step<0x143, 0xc>(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ void put64(unsigned long long* p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long get64(unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int kMaxPerThread = 8;   // n <= 8 * threads
+
+__global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    __shared__ unsigned long long s_key;
+    __shared__ unsigned long long s_wkey[16];    // first acceptance per wave of the window
+    __shared__ unsigned long long s_key;         // the grid-wide first acceptance
     __shared__ int s_ok;
     __shared__ int s_self[2];
-    __shared__ int s_ntie;
-    __shared__ unsigned long long s_tie_j[8];
-    __shared__ int s_tie_d[8];
-    __shared__ double s_tie_z[8];
+    __shared__ int s_ntie[2];                    // near ties of the window, by window parity
+    __shared__ unsigned long long s_tie_j[2][8];
+    __shared__ int s_tie_d[2][8];
+    __shared__ double s_tie_z[2][8];
     __shared__ Rec s_rec[kRec];
     __shared__ unsigned long long s_prof[QAP_PHASES];
 
@@ -148,8 +191,19 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
     const int Rw = (n - w + G - 1) / G;          // rows owned by this workgroup
     const int C = Rw;                             // columns s = w + G c of this workgroup (same count)
     const uint32_t m = (uint32_t)((int64_t)n * (n - 1) / 2);
-    Lds L;
-    dist_layout(n, G, q, smem, &L);
+    Lds L_;
+    dist_layout(n, G, q, smem, &L_);
+    // the LDS arrays as plain pointer values
+    int32_t* const lD = L_.D;
+    uint8_t* const lAb = L_.Ab;
+    uint8_t* const lBb = L_.Bb;
+    uint8_t* const lSu = L_.Su;
+    uint8_t* const lSv = L_.Sv;
+    uint8_t* const lTu = L_.Tu;
+    uint8_t* const lTv = L_.Tv;
+    uint32_t* const labp = L_.abp;
+    uint32_t* const lbbp = L_.bbp;
+    int16_t* const lps = L_.ps;
     DistWs* ws = a.ws;
     int* X = a.X;                                 // [2 parities][2 rows][n]
 
@@ -157,53 +211,62 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
     if (tid < QAP_PHASES) s_prof[tid] = 0;
     unsigned long long prof_last = prof ? clock64() : 0;
     const unsigned long long prof_start = prof_last;
-    auto mark = [&](int k) {
+    auto mark = [&](int k) __attribute__((always_inline)) {
         if (prof && tid == 0) {
             const unsigned long long now = clock64();
             atomicAdd(&s_prof[k], now - prof_last);
             prof_last = now;
         }
     };
-    auto bump = [&](int k, unsigned long long x) { if (prof && tid == 0) atomicAdd(&s_prof[k], x); };
+    auto bump = [&](int k, unsigned long long x) __attribute__((always_inline)) { if (prof && tid == 0) atomicAdd(&s_prof[k], x); };
 
     // ---------------------------------------------------------------- load
-    if (tid == 0) { s_ok = 1; s_ntie = 0; }
+    if (tid == 0) { s_ok = 1; s_ntie[0] = 0; s_ntie[1] = 0; }
     __syncthreads();
-    for (int e = tid; e < Rw * n; e += nt) {
-        const int lr = e / n, s = e - lr * n, r = w + G * lr;
-        int d = 0;
-        if (s > r) d = a.delta[rs32(n, r) + s - r - 1];
-        else if (s < r) d = a.delta[rs32(n, s) + r - s - 1];
-        L.D[e] = d;
-    }
-    for (int e = tid; e < Rw * P; e += nt) {
-        const int lr = e / P, k = e - lr * P, r = w + G * lr;
-        int av = 0, bv = 0;
-        if (k < n) {
-            av = a.A[r * n + k] - a.a_min;
-            bv = a.Bp[r * n + k] - a.b_min;
-            if ((av | bv) & ~0xff) s_ok = 0;
+    for (int lr = 0; lr < Rw; ++lr) {
+        const int r = w + G * lr;
+        const int32_t* up = a.delta + rs32(n, r) - r - 1;   // row r, s > r
+        for (int s = tid; s < n; s += nt) {
+            int d = 0;
+            if (s > r) d = up[s];
+            else if (s < r) d = a.delta[rs32(n, s) + r - s - 1];
+            lD[lr * n + s] = d;
         }
-        L.Ab[e] = (uint8_t)av;
-        L.Bb[e] = (uint8_t)bv;
+        for (int k = tid; k < P; k += nt) {
+            int av = 0, bv = 0;
+            if (k < n) {
+                av = a.A[r * n + k] - a.a_min;
+                bv = a.Bp[r * n + k] - a.b_min;
+                if ((av | bv) & ~0xff) s_ok = 0;
+            }
+            lAb[lr * P + k] = (uint8_t)av;
+            lBb[lr * P + k] = (uint8_t)bv;
+        }
     }
-    for (int k = tid; k < P; k += nt) { L.Su[k] = 0; L.Sv[k] = 0; L.Tu[k] = 0; L.Tv[k] = 0; }
+    for (int k = tid; k < P; k += nt) { lSu[k] = 0; lSv[k] = 0; lTu[k] = 0; lTv[k] = 0; }
     for (int i = tid; i < n; i += nt) {
         const int pi = a.p[i];
         if (pi < 0 || pi >= n) s_ok = 0;   // p indexes B below
-        L.ps[i] = (int16_t)pi;
+        lps[i] = (int16_t)pi;
     }
     const qap_chain_state st0 = *a.state;
     __syncthreads();
-    if (!s_ok || st0.status != QAP_OK) {
-        if (w == 0 && tid == 0) a.state->status = st0.status != QAP_OK ? st0.status : QAP_E_INVAL;
+    if (!s_ok || st0.status != QAP_OK || st0.mode == QAP_MODE_SCRATCH_STALE) {
+        if (w == 0 && tid == 0)
+            a.state->status = st0.status != QAP_OK ? st0.status
+                              : st0.mode == QAP_MODE_SCRATCH_STALE ? QAP_E_STATE : QAP_E_INVAL;
         return;   // every workgroup takes the same branch: the instance and state are shared
     }
     if (tid == 0) mark(QAP_PH_IO);
 
+    // kernel arguments used inside the helpers below, as plain values
     const uint64_t t_end = a.t_end;
     const double T0 = a.T0;
     const double* __restrict__ temps = a.temps;
+    const uint64_t seed = a.seed;
+    const uint32_t chain_id = a.chain_id;
+    const uint64_t spin_limit = a.spin_limit;
+    unsigned long long* const slot_base = a.slots;
     uint64_t t = st0.t;
     unsigned long long accepts = st0.accepts, hash = st0.hash, best_iter = st0.best_iter;
     long long cost = st0.cost, best = st0.best_cost;
@@ -211,34 +274,61 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
     int r0, s0;
     pair_of_u(n, idx0, r0, s0);
     unsigned long long epoch = 0;
-    int kb = 0, par = 0;
+    int par = 0;
     int pu = -1, pv = -1, pd = 0, ppar = 0;       // stale rows of the last swap, its Delta, its X parity
     uint32_t kwin = a.kmin;
     int nrec = 0;
+    int tb = 0;                                    // tie buffer of the current window
     bool alive = true;
 
-    auto grid_sync = [&]() -> bool {
+    // Publish this workgroup's first acceptance of the window (the minimum of
+    // its waves' keys, or none without a scan) and wait for every workgroup's;
+    // returns the grid-wide minimum (kNone if there is no acceptance).
+    // The caller's global stores (published Delta values) are complete before
+    // the slot is written, so a workgroup that has seen every slot of this
+    // window also sees them.  Slots alternate by window parity: a workgroup
+    // can be at most one window ahead of the slowest.
+    auto exchange = [&](bool with_scan) __attribute__((always_inline)) -> unsigned long long {
         wait_stores();
         __syncthreads();
-        if (tid == 0) {
-            epoch += 1;
-            const unsigned long long target = epoch * (unsigned long long)G;
-            __hip_atomic_fetch_add(&ws->count, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        epoch += 1;
+        const unsigned long long tag = (epoch & 1023ull) << 54;
+        unsigned long long* slots = slot_base + (epoch & 1) * kMaxGroups;
+        if (wave == 0) {
+            unsigned long long wk = ~0ull;
+            if (with_scan)
+                for (int i = lane; i < nwaves; i += 64) wk = s_wkey[i];
+            wk = wave_min_u64(wk);
+            const unsigned long long own = wk == ~0ull ? kNone : (wk & kKeyBits);
+            if (lane == 0) put64(&slots[w], tag | own);
             uint64_t spins = 0;
-            int ok = 1;
-            while (__hip_atomic_load(&ws->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            bool ok = true;
+            unsigned long long best_key;
+            for (;;) {
+                best_key = kNone;
+                bool all = true;
+                for (int i = lane; i < G; i += 64) {
+                    const unsigned long long x = get64(&slots[i]);
+                    all = all && (x >> 54) == (epoch & 1023ull);
+                    const unsigned long long k = x & kKeyBits;
+                    best_key = k < best_key ? k : best_key;
+                }
+                if (__all(all)) break;
+                if (++spins > spin_limit || get(&ws->err)) { ok = false; break; }
                 __builtin_amdgcn_s_sleep(1);
-                if (++spins > a.spin_limit || get(&ws->err)) { ok = 0; break; }
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            if (!ok) put(&ws->err, 1);
-            s_ok = ok;
+            best_key = wave_min_u64(best_key);
+            if (lane == 0) {
+                if (!ok) put(&ws->err, 1);
+                s_ok = ok;
+                s_key = best_key;
+            }
         }
         __syncthreads();
-        return s_ok != 0;
+        return s_key;
     };
 
-    auto flush = [&]() {
+    auto flush = [&]() __attribute__((always_inline)) {
         if (w == 0 && wave == 0) {
             uint64_t h = 0;
             if (lane < nrec) {
@@ -253,12 +343,14 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
         nrec = 0;
     };
 
-    auto refresh = [&]() {   // copy the published Delta(., u), Delta(., v) into stale own rows
+    // copy the published Delta(., u), Delta(., v) into stale own rows (after
+    // an exchange; the next scan, which reads these rows, follows a barrier)
+    auto refresh = [&]() __attribute__((always_inline)) {
         if (pu < 0) return;
         for (int which = 0; which < 2; ++which) {
             const int x = which == 0 ? pu : pv, y = which == 0 ? pv : pu;
             if (x % G != w) continue;
-            int32_t* row = L.D + (x / G) * n;
+            int32_t* row = lD + (x / G) * n;
             int* src = X + (ppar * 2 + which) * n;
             for (int s = tid; s < n; s += nt) {
                 if (s == x) row[s] = 0;
@@ -267,7 +359,6 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
             }
         }
         pu = pv = -1;
-        __syncthreads();
     };
 
     while (alive && t < t_end) {
@@ -275,18 +366,15 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
         const uint32_t W = (uint32_t)min<uint64_t>(min<uint64_t>((uint64_t)kwin, t_end - t), (uint64_t)m);
         const int32_t bound = reject_bound(temperature(temps, T0, t));
         unsigned long long mine = ~0ull;
-        __syncthreads();   // everyone has read the previous window's LDS results
-        if (tid == 0) { s_key = ~0ull; s_ntie = 0; }
-        __syncthreads();
-        auto test = [&](uint32_t j, int d) {
+        auto test = [&](uint32_t j, int d) __attribute__((always_inline)) {
             bool acc = d <= 0;
             if (!acc && d <= bound) {
                 const uint64_t tt = t + j;
                 double z;
-                acc = metropolis_positive(d, temperature(temps, T0, tt), uniform_r(a.seed, a.chain_id, tt), &z);
+                acc = metropolis_positive(d, temperature(temps, T0, tt), uniform_r(seed, chain_id, tt), &z);
                 if (fabs(z) < kNearTie) {
-                    const int slot = atomicAdd(&s_ntie, 1);
-                    if (slot < 8) { s_tie_j[slot] = j; s_tie_d[slot] = d; s_tie_z[slot] = z; }
+                    const int slot = atomicAdd(&s_ntie[tb], 1);
+                    if (slot < 8) { s_tie_j[tb][slot] = j; s_tie_d[tb][slot] = d; s_tie_z[tb][slot] = z; }
                 }
             }
             if (acc) {
@@ -294,6 +382,7 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
                 mine = key < mine ? key : mine;
             }
         };
+        __syncthreads();   // the last update's LDS writes are visible
         // proposals (r, s) with s owned here, r < s, in the window.  The rows of
         // the window are r0, r0 + 1, ... cyclically; row offset n - 1 is row r0
         // again, for a window that wraps round to the pairs before (r0, s0).
@@ -316,7 +405,7 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
                 if (!ok) continue;
                 const uint32_t j = (rs32(n, r) + (uint32_t)(s - r - 1) + m - idx0) % m;
                 if (j >= W) continue;
-                if (s != pu && s != pv) test(j, L.D[(s / G) * n + r]);
+                if (s != pu && s != pv) test(j, lD[(s / G) * n + r]);
                 else if (r == pu && s == pv) test(j, -pd);
             }
         }
@@ -326,31 +415,32 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
                 const int rr = w + G * (lr >> 1), x = (lr & 1) ? pv : pu;
                 if (rr == pu || rr == pv || x <= rr) continue;
                 const uint32_t j = (rs32(n, rr) + (uint32_t)(x - rr - 1) + m - idx0) % m;
-                if (j < W) test(j, L.D[(lr >> 1) * n + x]);
+                if (j < W) test(j, lD[(lr >> 1) * n + x]);
             }
         }
-        mine = wave_min64(mine);
-        if (lane == 0 && mine != ~0ull) atomicMin(&s_key, mine);
-        __syncthreads();
-        if (tid == 0 && s_key != ~0ull)
-            __hip_atomic_fetch_min(&ws->key[kb], s_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        {
+            const bool any = __ballot(mine != ~0ull) != 0;
+            const unsigned long long wk = any ? wave_min_u64(mine) : ~0ull;
+            if (lane == 0) s_wkey[wave] = wk;
+        }
         if (tid == 0) mark(QAP_PH_DELTA_SCAN);
-        alive = grid_sync();
+        const unsigned long long key = exchange(true);
+        alive = s_ok != 0;
         if (!alive) break;
-        const unsigned long long key = __hip_atomic_load(&ws->key[kb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (w == 0 && tid == 0)   // the buffer of two windows ago: everyone has read it by now
-            __hip_atomic_store(&ws->key[kb == 0 ? 2 : kb - 1], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        kb = kb == 2 ? 0 : kb + 1;
-        const uint32_t jstar = key == ~0ull ? UINT_MAX : (uint32_t)(key >> 32);
-        // near ties a sequential run would have met
-        const int ntie = min(s_ntie, 8);
-        if (tid < ntie && s_tie_j[tid] <= (jstar == UINT_MAX ? W - 1 : jstar)) {
+        refresh();   // the published values of the last swap are visible now
+        const uint32_t jstar = key == kNone ? UINT_MAX : (uint32_t)(key >> 32);
+        // near ties a sequential run would have met; the other buffer, read
+        // by everyone before this window's exchange, is cleared for the next
+        const int ntie = min(s_ntie[tb], 8);
+        if (tid < ntie && s_tie_j[tb][tid] <= (jstar == UINT_MAX ? W - 1 : jstar)) {
             const unsigned long long slot = atomicAdd((unsigned long long*)&ws->nties, 1ull);
             if (a.ties && st0.near_ties + slot < a.tie_cap)
-                a.ties[st0.near_ties + slot] = qap_near_tie{t + s_tie_j[tid], (int64_t)s_tie_d[tid], s_tie_z[tid]};
+                a.ties[st0.near_ties + slot] =
+                    qap_near_tie{t + s_tie_j[tb][tid], (int64_t)s_tie_d[tb][tid], s_tie_z[tb][tid]};
         }
-        if (tid == 0) { mark(QAP_PH_RESERVED); bump(QAP_PH_N_SCAN_STEPS, 1); }
-        refresh();
+        if (tid == 0) s_ntie[tb ^ 1] = 0;
+        tb ^= 1;
+        if (tid == 0) { mark(QAP_PH_GRID_SYNC); bump(QAP_PH_N_SCAN_STEPS, 1); }
         if (jstar == UINT_MAX) {
             t += W;
             idx0 = (uint32_t)(((uint64_t)idx0 + W) % m);
@@ -377,54 +467,82 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
             s_rec[nrec] = Rec{tstar, ((uint32_t)u << 16) | (uint32_t)v, dstar};
         }
         nrec += 1;
-        if (tid == 0) { const int16_t x = L.ps[u]; L.ps[u] = L.ps[v]; L.ps[v] = x; }
-        __syncthreads();
-        const int pu_new = L.ps[u], pv_new = L.ps[v];
-        for (int k = tid; k < n; k += nt) {
-            const int pk = L.ps[k];
-            L.Su[k] = (uint8_t)(a.A[u * n + k] - a.a_min);
-            L.Sv[k] = (uint8_t)(a.A[v * n + k] - a.a_min);
-            L.Tu[k] = (uint8_t)(a.B[pu_new * n + pk] - a.b_min);
-            L.Tv[k] = (uint8_t)(a.B[pv_new * n + pk] - a.b_min);
-        }
-        __syncthreads();
-        // own rows of B': rows u, v are replaced, the others swap columns u, v
-        for (int e = tid; e < Rw * n; e += nt) {
-            const int lr = e / n, k = e - lr * n, r = w + G * lr;
-            uint8_t* row = L.Bb + lr * P;
-            if (r == u) row[k] = L.Tu[k];
-            else if (r == v) row[k] = L.Tv[k];
-            else if (k == u) { const uint8_t x = row[u]; row[u] = row[v]; row[v] = x; }
-        }
-        for (int k = tid; k < n; k += nt) {
-            const int da = (int)L.Su[k] - (int)L.Sv[k], db = (int)L.Tu[k] - (int)L.Tv[k];
-            L.abp[k] = (uint32_t)(uint16_t)da | ((uint32_t)(uint16_t)da << 16);
-            L.bbp[k] = (uint32_t)(uint16_t)db | ((uint32_t)(uint16_t)db << 16);
-        }
-        if (wave == 0 || wave == (nwaves > 1 ? 1 : 0)) {
-            const uint8_t* x = (wave == 0) ? L.Su : L.Sv;
-            const uint8_t* y = (wave == 0) ? L.Tu : L.Tv;
-            uint32_t acc = 0;
-            for (int k = lane; k < q; k += 64) acc = dot4(((const uint32_t*)x)[k], ((const uint32_t*)y)[k], acc);
-            const int sd = wave_sum((int)acc);
-            if (lane == 0) s_self[wave == 0 ? 0 : 1] = sd;
-            if (nwaves == 1) {
-                uint32_t acc2 = 0;
-                for (int k = lane; k < q; k += 64) acc2 = dot4(((const uint32_t*)L.Sv)[k], ((const uint32_t*)L.Tv)[k], acc2);
-                const int sd2 = wave_sum((int)acc2);
-                if (lane == 0) s_self[1] = sd2;
+        // staged rows after the swap: A[u][.], A[v][.] and B'[u][.] = B[p(v)][p(.)],
+        // B'[v][.] = B[p(u)][p(.)] with p the permutation after the swap.  All
+        // global loads are issued before any result is used.
+        const int pu_new = lps[v], pv_new = lps[u];
+        int ga[kMaxPerThread], gb[kMaxPerThread], gc[kMaxPerThread], gd[kMaxPerThread];
+#pragma unroll
+        for (int i = 0; i < kMaxPerThread; ++i) {
+            const int k = tid + i * nt;
+            if (k < n) {
+                const int pk = k == u ? pu_new : (k == v ? pv_new : (int)lps[k]);
+                ga[i] = a.A[u * n + k];
+                gb[i] = a.A[v * n + k];
+                gc[i] = a.B[pu_new * n + pk];
+                gd[i] = a.B[pv_new * n + pk];
             }
+        }
+#pragma unroll
+        for (int i = 0; i < kMaxPerThread; ++i) {
+            const int k = tid + i * nt;
+            if (k < n) {
+                const int su = ga[i] - a.a_min, sv = gb[i] - a.a_min, tu = gc[i] - a.b_min, tv = gd[i] - a.b_min;
+                lSu[k] = (uint8_t)su;
+                lSv[k] = (uint8_t)sv;
+                lTu[k] = (uint8_t)tu;
+                lTv[k] = (uint8_t)tv;
+                const int da = su - sv, db = tu - tv;
+                labp[k] = (uint32_t)(uint16_t)da | ((uint32_t)(uint16_t)da << 16);
+                lbbp[k] = (uint32_t)(uint16_t)db | ((uint32_t)(uint16_t)db << 16);
+            }
+        }
+        __syncthreads();   // staged rows complete; everyone has read p
+        if (tid == 0) { lps[u] = (int16_t)pu_new; lps[v] = (int16_t)pv_new; }
+        // own rows of B': rows u, v are replaced, the others swap columns u, v
+        for (int lr = 0; lr < Rw; ++lr) {
+            const int r = w + G * lr;
+            uint8_t* row = lBb + lr * P;
+            if (r == u || r == v) {
+                const uint8_t* src = r == u ? lTu : lTv;
+                for (int k = tid; k < n; k += nt) row[k] = src[k];
+            } else if (tid == lr) {
+                const uint8_t x = row[u]; row[u] = row[v]; row[v] = x;
+            }
+        }
+        if (wave < 2) {   // self terms <A[x][.], B'[x][.]> of x = u, v
+            const uint32_t* x = (const uint32_t*)(wave == 0 ? lSu : lSv);
+            const uint32_t* y = (const uint32_t*)(wave == 0 ? lTu : lTv);
+            uint32_t acc = 0;
+            for (int k = lane; k < q; k += 64) acc = dot4(x[k], y[k], acc);
+            const int sd = wave_sum((int)acc);
+            if (lane == 0) s_self[wave] = sd;
         }
         if (nrec == kRec) flush();
         __syncthreads();
 
-        // pairs of own rows disjoint from {u, v}
-        for (int e = tid; e < Rw * n; e += nt) {
-            const int lr = e / n, s = e - lr * n, r = w + G * lr;
-            if (r == u || r == v || s == u || s == v || s == r) continue;
-            const v2i16 ar = __builtin_bit_cast(v2i16, L.abp[r]), as = __builtin_bit_cast(v2i16, L.abp[s]);
-            const v2i16 br = __builtin_bit_cast(v2i16, L.bbp[r]), bs = __builtin_bit_cast(v2i16, L.bbp[s]);
-            L.D[e] = __builtin_amdgcn_sdot2(ar - as, bs - br, L.D[e], false);
+        // pairs of own rows disjoint from {u, v}: lanes over columns, rows in turn
+        {
+            v2i16 as_[kMaxPerThread], bs_[kMaxPerThread];
+#pragma unroll
+            for (int i = 0; i < kMaxPerThread; ++i) {
+                const int s = tid + i * nt;
+                const bool ok = s < n && s != u && s != v;
+                as_[i] = __builtin_bit_cast(v2i16, ok ? labp[s] : 0u);
+                bs_[i] = __builtin_bit_cast(v2i16, ok ? lbbp[s] : 0u);
+            }
+            for (int lr = 0; lr < Rw; ++lr) {
+                const int r = w + G * lr;
+                if (r == u || r == v) continue;
+                const v2i16 ar = __builtin_bit_cast(v2i16, labp[r]), br = __builtin_bit_cast(v2i16, lbbp[r]);
+                int32_t* row = lD + lr * n;
+#pragma unroll
+                for (int i = 0; i < kMaxPerThread; ++i) {
+                    const int s = tid + i * nt;
+                    if (s < n && s != u && s != v && s != r)
+                        row[s] = __builtin_amdgcn_sdot2(ar - as_[i], bs_[i] - br, row[s], false);
+                }
+            }
         }
         // Delta(r, u), Delta(r, v) of own rows: one wave per row
         {
@@ -432,31 +550,30 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
             for (int lr = wave; lr < Rw; lr += nwaves) {
                 const int r = w + G * lr;
                 if (r == u || r == v) continue;
-                const uint32_t* ar = (const uint32_t*)(L.Ab + lr * P);
-                const uint32_t* br = (const uint32_t*)(L.Bb + lr * P);
+                const uint32_t* ar = (const uint32_t*)(lAb + lr * P);
+                const uint32_t* br = (const uint32_t*)(lBb + lr * P);
                 uint32_t pu_ = 0, pv_ = 0, self = 0;
                 for (int k = lane; k < q; k += 64) {
                     const uint32_t xa = ar[k], xb = br[k];
-                    pu_ = dot4(xa, ((const uint32_t*)L.Tu)[k], pu_);
-                    pu_ = dot4(((const uint32_t*)L.Su)[k], xb, pu_);
-                    pv_ = dot4(xa, ((const uint32_t*)L.Tv)[k], pv_);
-                    pv_ = dot4(((const uint32_t*)L.Sv)[k], xb, pv_);
+                    pu_ = dot4(xa, ((const uint32_t*)lTu)[k], pu_);
+                    pu_ = dot4(((const uint32_t*)lSu)[k], xb, pu_);
+                    pv_ = dot4(xa, ((const uint32_t*)lTv)[k], pv_);
+                    pv_ = dot4(((const uint32_t*)lSv)[k], xb, pv_);
                     self = dot4(xa, xb, self);
                 }
                 const int Pu = wave_sum((int)pu_), Pv = wave_sum((int)pv_), Sr = wave_sum((int)self);
                 if (lane == 0) {
-                    const uint8_t* A_r = L.Ab + lr * P;
-                    const uint8_t* B_r = L.Bb + lr * P;
-                    const int du = finish_sym(Pu - Sr - su, A_r[r], A_r[u], L.Su[r], L.Su[u], B_r[r], B_r[u], L.Tu[r], L.Tu[u]);
-                    const int dv = finish_sym(Pv - Sr - sv, A_r[r], A_r[v], L.Sv[r], L.Sv[v], B_r[r], B_r[v], L.Tv[r], L.Tv[v]);
-                    L.D[lr * n + u] = du;
-                    L.D[lr * n + v] = dv;
+                    const uint8_t* A_r = lAb + lr * P;
+                    const uint8_t* B_r = lBb + lr * P;
+                    const int du = finish_sym(Pu - Sr - su, A_r[r], A_r[u], lSu[r], lSu[u], B_r[r], B_r[u], lTu[r], lTu[u]);
+                    const int dv = finish_sym(Pv - Sr - sv, A_r[r], A_r[v], lSv[r], lSv[v], B_r[r], B_r[v], lTv[r], lTv[v]);
+                    lD[lr * n + u] = du;
+                    lD[lr * n + v] = dv;
                     put(X + (par * 2 + 0) * n + r, du);
                     put(X + (par * 2 + 1) * n + r, dv);
                 }
             }
         }
-        __syncthreads();
         pu = u; pv = v; pd = dstar; ppar = par;
         par ^= 1;
         t = tstar + 1;
@@ -468,19 +585,21 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
     }
 
     // ------------------------------------------------------------ write back
-    if (alive) alive = grid_sync();   // the last swap's published values
-    if (alive) refresh();
-    if (w == 0 && nrec > 0) flush();
-    for (int e = tid; e < Rw * n; e += nt) {
-        const int lr = e / n, s = e - lr * n, r = w + G * lr;
-        if (s > r) a.delta[rs32(n, r) + s - r - 1] = L.D[e];
+    if (alive) {   // the last swap's published values
+        exchange(false);
+        alive = s_ok != 0;
     }
-    for (int e = tid; e < Rw * n; e += nt) {
-        const int lr = e / n, k = e - lr * n, r = w + G * lr;
-        a.Bp[r * n + k] = (int32_t)L.Bb[lr * P + k] + a.b_min;
+    if (alive) refresh();
+    __syncthreads();
+    if (w == 0 && nrec > 0) flush();
+    for (int lr = 0; lr < Rw; ++lr) {
+        const int r = w + G * lr;
+        int32_t* up = a.delta + rs32(n, r) - r - 1;
+        for (int s = r + 1 + tid; s < n; s += nt) up[s] = lD[lr * n + s];
+        for (int k = tid; k < n; k += nt) a.Bp[r * n + k] = (int32_t)lBb[lr * P + k] + a.b_min;
     }
     if (w == 0) {
-        for (int i = tid; i < n; i += nt) a.p[i] = L.ps[i];
+        for (int i = tid; i < n; i += nt) a.p[i] = lps[i];
         if (tid == 0) {
             qap_chain_state st;
             st.t = t; st.accepts = accepts; st.hash = hash;
@@ -500,12 +619,13 @@ __global__ void __launch_bounds__(1024) k_chain_dist(DistArgs a)
     }
 }
 
-__global__ void k_ws_reset(DistWs* ws)
+__global__ void k_ws_reset(DistWs* ws, unsigned long long* slots)
 {
-    ws->count = 0;
-    ws->key[0] = ws->key[1] = ws->key[2] = ~0ull;
-    ws->err = 0;
-    ws->nties = 0;
+    for (int i = threadIdx.x; i < 2 * kMaxGroups; i += blockDim.x) slots[i] = 0;   // window 0 is never used
+    if (threadIdx.x == 0) {
+        ws->err = 0;
+        ws->nties = 0;
+    }
 }
 
 }  // namespace
@@ -525,7 +645,8 @@ int launch_chain_dist(const DistArgs& a0, int G, int threads, hipStream_t stream
     const void* fn = (const void*)k_chain_dist;
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
         return QAP_E_DEVICE;
-    hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(1), 0, stream, a.ws);
+    if (G > kMaxGroups || threads > 512 || a.n > kMaxPerThread * threads) return QAP_E_INVAL;
+    hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, stream, a.ws, a.slots);
     void* kargs[] = {&a};
     if (hipLaunchCooperativeKernel(fn, dim3(G), dim3(threads), kargs, (unsigned)bytes, stream) != hipSuccess)
         return QAP_E_DEVICE;

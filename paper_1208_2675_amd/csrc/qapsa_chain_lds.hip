@@ -99,7 +99,8 @@ __device__ void chain_body(const ChainArgs& a, char* smem)
         const qap_chain_state st = *a.state;
         s_t = st.t; s_acc = st.accepts; s_ties = st.near_ties; s_hash = st.hash;
         s_cost = st.cost; s_best = st.best_cost; s_best_iter = st.best_iter;
-        s_status = st.status;
+        s_status = st.status != QAP_OK ? st.status : (st.mode == QAP_MODE_SCRATCH_STALE ? (int)QAP_E_STATE : QAP_OK);
+        if (st.status == QAP_OK && s_status != QAP_OK) a.state->status = s_status;
         s_min[0] = s_min[1] = s_min[2] = UINT_MAX;
     }
     __syncthreads();

@@ -61,15 +61,22 @@ int launch_chain_lds(const ChainArgs& a, bool symmetric, bool a_in_lds, int thre
 
 // Global workspace of the multi-workgroup kernel (one per chain, caller memory).
 struct DistWs {
-    unsigned long long count;    // grid barrier arrivals
-    unsigned long long key[3];   // first acceptance of a scan window, min-reduced
     unsigned long long nties;    // near ties logged by this call
-    int err;                     // a barrier timed out
-    int pad[5];
+    int err;                     // a workgroup gave up waiting for the others
+    int pad[13];
 };
 static_assert(sizeof(DistWs) == 64, "workspace header");
 
-inline size_t dist_ws_bytes(int n) { return sizeof(DistWs) + 4 * sizeof(int) * (size_t)n; }
+// Multi-workgroup exchange area: the header, two sets (by window parity) of
+// one 64-bit slot per workgroup, then the published Delta values (two swap
+// parities x rows u, v x n).
+constexpr int kMaxGroups = 1024;
+inline size_t dist_ws_bytes(int n)
+{
+    return sizeof(DistWs) + 2 * kMaxGroups * sizeof(unsigned long long) + 4 * sizeof(int) * (size_t)n;
+}
+inline unsigned long long* dist_slots(void* ws) { return (unsigned long long*)((char*)ws + sizeof(DistWs)); }
+inline int* dist_X(void* ws) { return (int*)(dist_slots(ws) + 2 * kMaxGroups); }
 
 struct DistArgs {
     int32_t n;
@@ -95,6 +102,7 @@ struct DistArgs {
     uint32_t chain_id;
     uint32_t tie_cap;
     DistWs* ws;
+    unsigned long long* slots;   // [2][kMaxGroups]
     int* X;
 };
 
@@ -104,8 +112,8 @@ int launch_chain_dist(const DistArgs& a, int G, int threads, hipStream_t stream)
 
 // batched chains (one persistent launch, a device-wide work queue)
 struct BatchWs {
-    unsigned next[2];   // queue positions of the LDS-resident and the scratch-backed kernel
-    unsigned pad[14];
+    unsigned next[4];   // queue positions of the kernels of placement 0 .. 3
+    unsigned pad[12];
 };
 struct BatchArgs {
     int32_t n_chains;
@@ -118,15 +126,20 @@ struct BatchArgs {
 };
 // groups <= 0: as many workgroups as can be resident at once (occupancy of each
 // kernel at its LDS size times the CU count), never more than its chains
-int launch_chain_batch(const BatchArgs& b, int groups, int count_lds, int count_gmem, int threads,
-                       size_t lds_bytes, size_t gmem_lds_bytes, hipStream_t stream);
+int launch_chain_batch(const BatchArgs& b, int groups, const int count[4], int threads, const size_t lds[4],
+                       hipStream_t stream);
 // a second stream (default priority) and two events of the current device, created once
-int side_stream(hipStream_t* side, hipEvent_t* fork, hipEvent_t* join);
+int side_stream(int which, hipStream_t* side, hipEvent_t* fork, hipEvent_t* join);
 
 // byte-valued chain kernel (scratch and Delta modes)
 int wg_quads(int n);
-size_t lds_wg_bytes(int n, bool symmetric, bool gmem = false);
-size_t wg_scratch_bytes(int n, bool symmetric);
-int launch_chain_wg(const ChainArgs& a, bool symmetric, int threads, hipStream_t stream);
+// Placement of the one-workgroup kernel's state: 0 all in LDS, 1 Delta in
+// device memory (the caller's buffer), 2 also the byte copies of A in a
+// device scratch of wg_scratch_bytes, 3 also those of B'; -1 if the small
+// per-chain vectors alone do not fit.
+int wg_place(int n, bool symmetric);
+size_t lds_wg_bytes(int n, bool symmetric, int place);
+size_t wg_scratch_bytes(int n, bool symmetric, int place);
+int launch_chain_wg(const ChainArgs& a, bool symmetric, int place, hipStream_t stream);
 
 }  // namespace qapsa

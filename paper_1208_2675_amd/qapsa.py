@@ -21,8 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libqapsa.so")
 
 QAP_OK, QAP_E_INVAL, QAP_E_NOT_PERM, QAP_E_RANGE = 0, -1, -2, -3
 QAP_E_NOMEM, QAP_E_DEVICE, QAP_E_UNSUPPORTED, QAP_E_STATE, QAP_E_TIMEOUT = -4, -5, -6, -7, -8
-QAP_MODE_SCRATCH, QAP_MODE_DELTA = 0, 1
-QAP_FLAG_DELTA_ONLY, QAP_FLAG_SCRATCH_ONLY = 1, 2
+QAP_MODE_SCRATCH, QAP_MODE_DELTA, QAP_MODE_SCRATCH_STALE = 0, 1, 2
+QAP_FLAG_DELTA_ONLY, QAP_FLAG_SCRATCH_ONLY, QAP_FLAG_MULTI_WG = 1, 2, 4
 
 
 class QapError(RuntimeError):
@@ -61,7 +61,7 @@ class RunBuffers(C.Structure):
 
 PHASES = ["total", "scratch_thresh", "scratch_eval", "scratch_accept", "delta_scan", "delta_update", "build",
           "io", "n_rounds", "n_scratch_acc", "n_scan_steps", "n_delta_acc", "n_thresh", "switch_t", "n_scanned",
-          "reserved"]
+          "grid_sync"]
 
 
 STATE_BYTES = C.sizeof(ChainState)
@@ -225,7 +225,7 @@ class Chain:
     def phases(self) -> dict:
         """Phase counters of the runs so far (cycles of the shader clock, counts)."""
         v = self.prof.cpu().numpy().tolist()
-        return {k: int(x) for k, x in zip(PHASES, v) if k != "reserved"}
+        return {k: int(x) for k, x in zip(PHASES, v)}
 
     def run(self, t_end: int | None = None):
         self.sched.t_end = self.iters if t_end is None else int(t_end)
@@ -418,4 +418,4 @@ class Batch:
 
     def phases(self) -> dict:
         v = self.prof.cpu().numpy().tolist()
-        return {k: int(x) for k, x in zip(PHASES, v) if k != "reserved"}
+        return {k: int(x) for k, x in zip(PHASES, v)}

@@ -1,12 +1,12 @@
 """Write tests/golden/oracle_runs.json: expected results of full-size runs,
 computed by the CPU oracle only (nothing here touches the device library).
 
-    python tests/golden/make_golden.py            # single-chain workloads
-    python tests/golden/make_golden.py --mix      # also the 512-chain mix (slow)
+    python tests/golden/make_golden.py                 # single-chain workloads
+    python tests/golden/make_golden.py --mix --no-single   # the 512-chain mix (minutes, all cores)
 
 Each entry records the schedule (T0 = mean |Delta_0|, alpha), the final state
-(accepts, FNV hash of the accepted swaps, cost, best cost and its iteration),
-the final permutation and the near ties of Eq. (2).
+(accepts, trajectory hash of the accepted swaps, cost, best cost and its
+iteration), the final permutation (single chains) and the near ties of Eq. (2).
 """
 from __future__ import annotations
 
@@ -64,12 +64,13 @@ def main():
     global _MIX
     ap = argparse.ArgumentParser()
     ap.add_argument("--mix", action="store_true")
+    ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--jobs", type=int, default=min(8, os.cpu_count() or 1))
     args = ap.parse_args()
     oracle.build()
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     with ProcessPoolExecutor(args.jobs) as ex:
-        for key, res in ex.map(_single, SINGLE):
+        for key, res in ex.map(_single, [] if args.no_single else SINGLE):
             data[key] = res
             print(key, res["accepts"], res["cost"], res["oracle_seconds"], flush=True)
     if args.mix:

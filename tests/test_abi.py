@@ -63,11 +63,15 @@ def test_host_side_argument_errors(qlib):
     assert Q.qap_temp_table_len(10**9) == 2048 + 954
     assert Q.qap_temp_table_len(1) == 2049
     q = lambda n: (((n + 3) // 4) | 1) * 4
-    for n in (2, 150, 2000):
-        assert Q.qap_workspace_bytes(n) == max(64 + 16 * n, 2 * n * q(n))
+    for n in (2, 150):   # everything in LDS: the multi-workgroup exchange area is the larger
+        assert Q.qap_workspace_bytes(n) == 64 + 2 * 1024 * 8 + 16 * n
+    # n = 2000: A, A^T, B', B'^T as bytes in device scratch (asymmetric chain)
+    assert Q.qap_workspace_bytes(2000) == 4 * 2000 * q(2000)
     assert Q.qap_single_workgroup(150, 0, 99, 23) == 1 and Q.qap_single_workgroup(195, 1, 99, 99) == 1
-    assert Q.qap_single_workgroup(200, 0, 99, 27) == 2 and Q.qap_single_workgroup(2000, 1, 99, 141) == 0
+    assert Q.qap_single_workgroup(200, 0, 99, 27) == 2 and Q.qap_single_workgroup(2000, 1, 99, 141) == 2
+    assert Q.qap_single_workgroup(20000, 1, 99, 99) == 0
     assert Q.qap_chain_scratch_bytes(200, 0) == 2 * 200 * 204
+    assert Q.qap_chain_scratch_bytes(150, 0) == 0 and Q.qap_chain_scratch_bytes(512, 1) == 2 * 512 * q(512)
     assert Q.qap_single_workgroup(100, 1, 300, 9) == 0
     fake = 0x1000  # never dereferenced: every call below is rejected first
     assert Q.qap_sa_run(8, fake, None, fake, fake, fake, fake, Q.Schedule(100, 100, 1.0, 0.99, 1, 0, 0, 0, 0),
@@ -80,6 +84,7 @@ def test_host_side_argument_errors(qlib):
                 Q.Schedule(100, 100, float("nan"), 0.99, 1, 0, 0, 0, 0),
                 Q.Schedule(100, 100, 1.0, 1.5, 1, 0, 0, 0, 0), Q.Schedule(0, 0, 1.0, 0.5, 1, 0, 0, 0, 0),
                 Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 7, 0, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 3, 0, 0),
+                Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 8, 0, 0),
                 Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 0, 1001, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 0, 0, 1)):
         assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, fake, bad, info, bufs, 0) == Q.QAP_E_INVAL
     assert Q.qap_sa_run(8, fake, fake, None, fake, fake, fake, ok, info, bufs, 0) == Q.QAP_E_INVAL
@@ -91,6 +96,10 @@ def test_host_side_argument_errors(qlib):
     # values outside the 16-bit working range have no single-workgroup kernel
     wide = Q.InstanceInfo(0, 0, 0, 70000, 0, 9, 1, 0)
     assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, fake, ok, wide, bufs, 0) == Q.QAP_E_UNSUPPORTED
+    # batches run four waves per chain: other workgroup sizes are refused
+    one = (Q.ChainDesc * 1)()
+    assert Q.qap_sa_run_batch(1, one, fake, None, Q.BatchConfig(128, 0, 0, None), fake, 0) == Q.QAP_E_INVAL
+    assert Q.qap_sa_run_batch(-1, one, fake, None, Q.BatchConfig(256, 0, 0, None), fake, 0) == Q.QAP_E_INVAL
     assert Q.qap_cost(0, fake, fake, fake, fake, 0) == Q.QAP_E_INVAL
     assert Q.qap_delta_init(1, fake, fake, fake, fake, fake, fake, None, 0) == Q.QAP_E_INVAL
     assert Q.qap_schedule_tables(0, 0.5, fake, 0) == Q.QAP_E_INVAL

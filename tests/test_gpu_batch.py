@@ -34,12 +34,12 @@ def _check(orc, Q, b, refs):
         assert np.array_equal(b.perm(i), ref["p"]), (i, ch.name)
 
 
-@pytest.mark.parametrize("threads", [64, 256])
-def test_batch_matches_oracle_per_chain(orc, Q, threads):
+@pytest.mark.parametrize("groups", [0, 5])
+def test_batch_matches_oracle_per_chain(orc, Q, groups):
     chains = _mix(30000)
     refs = [_oracle(orc, ch) for ch in chains]
     b = Q.Batch(chains).init()
-    b.run(threads=threads)
+    b.run(groups=groups)
     _check(orc, Q, b, refs)
 
 
@@ -64,6 +64,6 @@ def test_batch_alone_equals_mixed(Q):
     sm = mixed.states()
     for i in (0, 5, 11):
         alone = Q.Batch([chains[i]]).init()
-        alone.run(threads=128)
+        alone.run(groups=1)
         assert alone.states()[0] == sm[i]
         assert np.array_equal(alone.perm(0), mixed.perm(i))

@@ -1,5 +1,6 @@
 """Parity of the multi-workgroup chain kernel (symmetric instances too large
-for one CU) with the CPU oracle, and at N=2000 against stored oracle results."""
+for one CU, and smaller ones sent there by QAP_FLAG_MULTI_WG) with the CPU
+oracle, and at N=2000 against stored oracle results."""
 import json
 import math
 import os
@@ -35,7 +36,7 @@ def _run_compare(orc, Q, A, B, p0, iters, seed, T0=None, slices=(), acc_cap=512,
     s = orc.schedule(A, B, p0, iters)
     T0o = s["T0"] if T0 is None else T0
     ref = orc.sa_run(A, B, p0, iters, T0o, s["alpha"], seed, 0, acc_cap=acc_cap, tie_cap=64)
-    c = Q.Chain(A, B, p0, iters, seed, 0, T0=T0, accept_cap=acc_cap).init()
+    c = Q.Chain(A, B, p0, iters, seed, 0, T0=T0, accept_cap=acc_cap, flags=Q.QAP_FLAG_MULTI_WG).init()
     for t_end in list(slices) + [iters]:
         c.run(t_end)
     got = c.result(with_delta=True)
@@ -92,3 +93,16 @@ def test_dist_n2000_prefix_golden(orc, Q):
         a_, b_ = sorted(rng.choice(n, 2, replace=False))
         idx = a_ * (2 * n - a_ - 1) // 2 + b_ - a_ - 1
         assert r["delta"][idx] == orc.swap_cost(ch.A, ch.B, r["p"], int(a_), int(b_))
+
+
+def test_dist_refuses_stale_delta(Q):
+    """A chain that stopped in scratch mode mid-schedule leaves Delta stale; the
+    multi-workgroup kernel, which needs Delta, reports QAP_E_STATE."""
+    A, B, p0 = _sym(220, 64)
+    c = Q.Chain(A, B, p0, 50000, 5, 0, flags=Q.QAP_FLAG_SCRATCH_ONLY).init()
+    c.run(1000)
+    st = c.state()
+    assert st.mode == Q.QAP_MODE_SCRATCH_STALE and st.status == 0
+    c.sched.flags = Q.QAP_FLAG_MULTI_WG
+    c.run(2000)
+    assert c.state().status == Q.QAP_E_STATE

@@ -153,6 +153,29 @@ def test_chain_slices_are_seamless(orc, Q, switch):
     _compare_run(orc, Q, A, B, p0, 50000, seed=3, slices=[1, 777, 20000, 20001, 49999], switch_permille=switch)
 
 
+def test_stale_delta_between_scratch_slices(orc, Q):
+    """A call that stops in scratch mode leaves Delta stale (and says so); a
+    later call that needs Delta rebuilds it, so the trajectory and the final
+    Delta are unchanged."""
+    A, B, p0 = _inst(60, 81)
+    s = orc.schedule(A, B, p0, 40000)
+    ref = orc.sa_run(A, B, p0, 40000, s["T0"], s["alpha"], 4, 0)
+    c = Q.Chain(A, B, p0, 40000, 4, 0, flags=Q.QAP_FLAG_SCRATCH_ONLY).init()
+    c.run(10000)
+    assert c.state().mode == Q.QAP_MODE_SCRATCH_STALE
+    c.sched.flags = Q.QAP_FLAG_DELTA_ONLY
+    c.run(25000)
+    assert c.state().mode == Q.QAP_MODE_DELTA
+    c.sched.flags = Q.QAP_FLAG_SCRATCH_ONLY
+    c.run()
+    got = c.result(with_delta=True)
+    assert got["mode"] == Q.QAP_MODE_SCRATCH
+    for k in ("t", "accepts", "hash", "cost", "best_cost", "best_iter", "near_ties"):
+        assert got[k] == ref[k], k
+    assert np.array_equal(got["p"], ref["p"])
+    assert np.array_equal(got["delta"], orc.delta_matrix(A, B, got["p"]))
+
+
 def test_chain_n32_full(orc, Q, golden):
     ch = W.single_chain("n32_sym")
     _compare_run(orc, Q, ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, acc_cap=1000)

@@ -18,14 +18,26 @@ def Q():
     return qapsa
 
 
-def _trace(k, iters, n_lo=32, n_hi=300, rate=2000.0, seed=41):
-    return W.served_trace(n_requests=k, rate=rate, iters=iters, n_lo=n_lo, n_hi=n_hi, seed=seed)
+def _trace(k, iters, n_lo=32, n_hi=300, rate=2000.0, seed=41, force=()):
+    """Served trace; ``force`` maps request positions to instance sizes so that
+    each kind of kernel (whole chain in LDS, chain with device scratch,
+    multi-workgroup) is sure to take part."""
+    reqs = W.served_trace(n_requests=k, rate=rate, iters=iters, n_lo=n_lo, n_hi=n_hi, seed=seed)
+    for j, n in force:
+        ch = reqs[j].chain
+        A, B = W.sym_uniform(n, 7000 + j)
+        reqs[j].chain = W.Chain(f"req{j}", A, B, W.random_perm(n, 7001 + j), ch.iters, ch.philox_seed,
+                                ch.chain_id, True, {"kind": "sym_uniform"})
+    return reqs
 
 
 def test_served_equals_alone_and_oracle(orc, Q):
     from paper_1208_2675_amd.serve import Server
-    reqs = _trace(16, 60000)
-    assert any(not Q.fits_one_workgroup(q.chain.n, True, 99, 99) for q in reqs)   # both kernels take part
+    reqs = _trace(16, 60000, force=((3, 470), (5, 260), (6, 90)))
+    # chains wholly in LDS and chains with matrices in device scratch both take
+    # part (n = 470: A and B' both in scratch)
+    kinds = {Q.qap_single_workgroup(q.chain.n, 1, 99, 99) for q in reqs}
+    assert kinds == {1, 2}, kinds
     srv = Server(max_slots=6, slice_iters=7000)
     st = srv.run_trace(reqs, time_limit=300)
     assert len(st.results) == len(reqs)
