@@ -105,11 +105,15 @@ def section_single(Q, W, torch, args):
 
 
 def section_batched(Q, W, torch, args):
+    from paper_1208_2675_amd import tune
     chains = W.batched_mix(iters=args.batch_iters)
     fits = [ch for ch in chains
             if Q.fits_one_workgroup(ch.n, ch.symmetric, int(ch.A.max() - ch.A.min()), int(ch.B.max() - ch.B.min()))]
     log(f"batched: {len(fits)} of {len(chains)} chains, I={args.batch_iters:.0e}")
-    b = Q.Batch(fits).init()
+    t_tune = time.perf_counter()
+    table = tune.load_or_tune(iters=args.batch_iters, log=log)
+    t_tune = time.perf_counter() - t_tune
+    b = Q.Batch(fits).init(switch_permille=lambda n, sym: tune.switch_for(table, n, sym))
     # largest expected work first
     import numpy as np
     order = torch.tensor(np.argsort([-(ch.n * ch.n) for ch in fits]).astype(np.int32), device="cuda")
@@ -124,9 +128,19 @@ def section_batched(Q, W, torch, args):
     sts = b.states()
     iters = sum(ch.iters for ch in fits)
     acc = sum(s["accepts"] for s in sts)
+    parity = None
+    gold_path = os.path.join(ROOT, "tests", "golden", "oracle_runs.json")
+    if os.path.exists(gold_path) and len(fits) == len(chains) and args.batch_iters == 10**7:
+        gold = json.load(open(gold_path)).get("mix512", {}).get("chains")
+        if gold and len(gold) == len(sts):
+            parity = all(all(st[k] == g[k] for k in ("accepts", "hash", "cost", "best_cost", "best_iter"))
+                         for st, g in zip(sts, gold))
     return {"chains": len(fits), "chains_total": len(chains), "iters": iters, "wall_s": wall,
             "kernel_ms": ev0.elapsed_time(ev1), "value": iters / wall, "delta_updates_per_s": acc / wall,
-            "unsupported_chains": len(chains) - len(fits)}
+            "unsupported_chains": len(chains) - len(fits), "tuning_s": round(t_tune, 2),
+            "parity_vs_oracle": parity,
+            "switch_permille": {f"{x['lo']}-{x['hi']}{'s' if x['symmetric'] else 'a'}": x["switch_permille"]
+                                for x in table["buckets"]}}
 
 
 def section_update(Q, W, torch, args):

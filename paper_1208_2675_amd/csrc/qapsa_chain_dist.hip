@@ -34,7 +34,16 @@ namespace {
 
 typedef short v2i16 __attribute__((ext_vector_type(2)));
 
+// Wave-uniform copies (scalar registers) of values the workgroup agrees on but
+// that come back from LDS, so that what derives from them stays scalar.
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ unsigned long long uni64(unsigned long long x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
 __device__ __forceinline__ uint32_t dot4(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_udot4(a, b, c, false); }
 
 __device__ __forceinline__ int wave_sum(int v)
@@ -170,6 +179,14 @@ __device__ __forceinline__ unsigned long long get64(unsigned long long* p)
 }
 
 constexpr int kMaxPerThread = 8;   // n <= 8 * threads
+
+// Eq. (2) for Delta > 0 at iteration t, out of line (keeps the FP64 log and the
+// generator from occupying scalar registers across the kernel).
+__device__ __noinline__ bool exact_test(int d, const double* temps, double T0, uint64_t seed, uint32_t chain,
+                                        uint64_t t, double* z)
+{
+    return metropolis_positive(d, temperature(temps, T0, t), uniform_r(seed, chain, t), z);
+}
 
 __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
 {
@@ -325,7 +342,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             }
         }
         __syncthreads();
-        return s_key;
+        return uni64(s_key);
     };
 
     auto flush = [&]() __attribute__((always_inline)) {
@@ -369,9 +386,8 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         auto test = [&](uint32_t j, int d) __attribute__((always_inline)) {
             bool acc = d <= 0;
             if (!acc && d <= bound) {
-                const uint64_t tt = t + j;
                 double z;
-                acc = metropolis_positive(d, temperature(temps, T0, tt), uniform_r(seed, chain_id, tt), &z);
+                acc = exact_test(d, temps, T0, seed, chain_id, t + j, &z);
                 if (fabs(z) < kNearTie) {
                     const int slot = atomicAdd(&s_ntie[tb], 1);
                     if (slot < 8) { s_tie_j[tb][slot] = j; s_tie_d[tb][slot] = d; s_tie_z[tb][slot] = z; }
@@ -425,7 +441,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         }
         if (tid == 0) mark(QAP_PH_DELTA_SCAN);
         const unsigned long long key = exchange(true);
-        alive = s_ok != 0;
+        alive = uni(s_ok) != 0;
         if (!alive) break;
         refresh();   // the published values of the last swap are visible now
         const uint32_t jstar = key == kNone ? UINT_MAX : (uint32_t)(key >> 32);
@@ -443,8 +459,10 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         if (tid == 0) { mark(QAP_PH_GRID_SYNC); bump(QAP_PH_N_SCAN_STEPS, 1); }
         if (jstar == UINT_MAX) {
             t += W;
-            idx0 = (uint32_t)(((uint64_t)idx0 + W) % m);
+            idx0 = uni((uint32_t)(((uint64_t)idx0 + W) % m));
             pair_of_u(n, idx0, r0, s0);
+            r0 = uni(r0);
+            s0 = uni(s0);
             kwin = min<uint64_t>((uint64_t)kwin * 2, (uint64_t)a.kmax);
             continue;
         }
@@ -454,8 +472,11 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         const uint64_t tstar = t + jstar;
         uint32_t istar = idx0 + jstar;
         if (istar >= m) istar -= m;
+        istar = uni(istar);
         int u, v;
         pair_of_u(n, istar, u, v);
+        u = uni(u);
+        v = uni(v);
         cost += dstar;
         accepts += 1;
         if (cost < best) { best = cost; best_iter = tstar + 1; }
@@ -470,7 +491,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         // staged rows after the swap: A[u][.], A[v][.] and B'[u][.] = B[p(v)][p(.)],
         // B'[v][.] = B[p(u)][p(.)] with p the permutation after the swap.  All
         // global loads are issued before any result is used.
-        const int pu_new = lps[v], pv_new = lps[u];
+        const int pu_new = uni((int)lps[v]), pv_new = uni((int)lps[u]);
         int ga[kMaxPerThread], gb[kMaxPerThread], gc[kMaxPerThread], gd[kMaxPerThread];
 #pragma unroll
         for (int i = 0; i < kMaxPerThread; ++i) {
@@ -546,7 +567,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         }
         // Delta(r, u), Delta(r, v) of own rows: one wave per row
         {
-            const int su = s_self[0], sv = s_self[1];
+            const int su = uni(s_self[0]), sv = uni(s_self[1]);
             for (int lr = wave; lr < Rw; lr += nwaves) {
                 const int r = w + G * lr;
                 if (r == u || r == v) continue;

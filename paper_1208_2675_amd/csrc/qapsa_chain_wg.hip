@@ -211,8 +211,18 @@ __device__ __forceinline__ int finish_delta(int S, int arr, int ars, int asr, in
     }
 }
 
-// Wave-uniform copies of values (scalar registers).
+// Wave-uniform copies of values (scalar registers).  Values the whole
+// workgroup agrees on but that come back from LDS would otherwise be treated
+// as per-lane, and everything derived from them (the proposal cursor, row
+// addresses) would run on the vector unit.
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ unsigned long long uni64(unsigned long long x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
 
 // Packed offset of row r (32-bit; the one-workgroup kernel has n <= 512).
 __host__ __device__ __forceinline__ uint32_t rs32(int n, int r) { return (uint32_t)r * (uint32_t)(2 * n - r - 1) >> 1; }
@@ -239,6 +249,32 @@ __device__ __forceinline__ void advance_by(int n, int& r, int& s, int k)
         if (++r == n - 1) r = 0;
         s = r + 1 + over;
     }
+}
+
+// Eq. (2) for Delta > 0 at iteration t, out of line: it is the rare path of
+// the scratch rounds and of the scan, and inlined copies of the FP64 log and
+// the generator cost scalar registers everywhere else.
+__device__ __noinline__ bool exact_test(int d, const double* temps, double T0, uint64_t seed, uint32_t chain,
+                                        uint64_t t, double* z)
+{
+    return metropolis_positive(d, temperature(temps, T0, t), uniform_r(seed, chain, t), z);
+}
+
+// Acceptance threshold of iteration t: the largest Delta that Eq. (2) accepts
+// (Eq. (2) is monotone in Delta).  *exact is set when T_t is so large that
+// near ties cannot be located from the threshold alone.
+__device__ __noinline__ int32_t threshold_at(const double* temps, double T0, uint64_t seed, uint32_t chain,
+                                             uint64_t t, bool* exact)
+{
+    const double T = temperature(temps, T0, t);
+    const double y = log(uniform_r(seed, chain, t));
+    if (!(T <= 1e9)) *exact = true;
+    const double xs = -y * T;
+    int64_t d = xs >= 2147483647.0 ? 2147483647 : (int64_t)xs;
+    auto acc = [&](int64_t dd) { return dd <= 0 || ((double)dd / T + y) < 0.0; };
+    while (d < 2147483647 && acc(d + 1)) ++d;
+    while (d > 0 && !acc(d)) --d;
+    return (int32_t)d;
 }
 
 template <bool SYM, int PL>
@@ -422,6 +458,8 @@ struct Chain {
         int sx = 0, sy = 0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) { sx += p0[w * n + x]; sy += p1[w * n + y]; }
+        sx = uni(sx);
+        sy = uni(sy);
         for (int s = tid; s < n; s += kThreads) {
             int tx = 0, ty = 0;
 #pragma unroll
@@ -447,37 +485,27 @@ struct Chain {
             __syncthreads();
         }
     }
-
-    // Acceptance threshold of iteration t: the largest Delta that Eq. (2) accepts
-    // (Eq. (2) is monotone in Delta).  *exact is set when T_t is so large that
-    // near ties cannot be located from the threshold alone.
-    __device__ int32_t threshold(const ChainArgs& a, uint64_t t, bool* exact) const
-    {
-        const double T = temperature(a.temps, a.T0, t);
-        const double y = log(uniform_r(a.seed, a.chain_id, t));
-        if (!(T <= 1e9)) *exact = true;
-        const double xs = -y * T;
-        int64_t d = xs >= 2147483647.0 ? 2147483647 : (int64_t)xs;
-        auto acc = [&](int64_t dd) { return dd <= 0 || ((double)dd / T + y) < 0.0; };
-        while (d < 2147483647 && acc(d + 1)) ++d;
-        while (d > 0 && !acc(d)) --d;
-        return (int32_t)d;
-    }
 };
 
 template <int V> struct IC { static constexpr int value = V; };
 
 template <bool SYM, int PL>
-__device__ void chain_run(const ChainArgs& a, char* smem)
+__device__ void chain_run(const ChainArgs& a_in, char* smem)
 {
-    // Cross-wave exchange only; the chain's scalars live in registers of every
-    // thread (all threads follow the same uniform control flow and apply the
-    // same updates).
+    // The chain's hot scalars live in scalar registers of every wave (all
+    // threads follow the same uniform control flow and apply the same
+    // updates).  Scalar registers are scarce (102), so cold arguments are read
+    // from an LDS copy where they are used and the running statistics are
+    // kept by thread 0 alone.
     __shared__ unsigned long long s_wkey[2][kWaves];   // per-wave first acceptance (j << 32 | Delta), by round parity
     __shared__ unsigned long long s_ties;
     __shared__ int s_flag;
     __shared__ unsigned long long s_prof[QAP_PHASES];
+    __shared__ ChainArgs s_arg;
 
+    if (threadIdx.x == 0) s_arg = a_in;
+    __syncthreads();
+    const ChainArgs& a = s_arg;
     Chain<SYM, PL> C(a, smem);
     const Wg& L = C.L;
     const int n = C.n, P = C.P, tid = C.tid, lane = C.lane, wave = C.wave;
@@ -538,23 +566,22 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
     }
     mark(QAP_PH_IO);
 
-    // arguments used in the loop, as plain values
-    const uint64_t t_end = a.t_end, iters = a.iters;
+    // hot arguments as plain values
+    const uint64_t t_end = uni64(a.t_end);
     const double T0 = a.T0;
     const double* __restrict__ temps = a.temps;
     const uint64_t seed = a.seed;
     const uint32_t chain_id = a.chain_id;
-    const uint32_t flags = a.flags, switch_permille = a.switch_permille;
-    const int max_step = a.max_step;
-    int64_t* const acc_log = a.acc_log;
-    const uint64_t acc_cap = a.acc_cap;
-    qap_near_tie* const ties = a.ties;
-    const uint64_t tie_cap = a.tie_cap;
 
     const uint32_t nt_mod = (uint32_t)kThreads % m;
-    uint64_t t = st0.t;
-    unsigned long long accepts = st0.accepts, hash = st0.hash, best_iter = st0.best_iter;
-    long long cost = st0.cost, best = st0.best_cost;
+    uint64_t t = uni64(st0.t);
+    // running statistics: thread 0's registers only
+    unsigned long long accepts = 0, hash = 0, best_iter = 0;
+    long long cost = 0, best = 0;
+    if (tid == 0) {
+        accepts = st0.accepts; hash = st0.hash; best_iter = st0.best_iter;
+        cost = st0.cost; best = st0.best_cost;
+    }
     int nrec = 0;
     uint32_t idx0 = (uint32_t)(t % m);      // packed index proposed at iteration t
     int r0, s0;                              // its pair
@@ -564,7 +591,7 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
     int kw = 1;                              // proposals per wave in a scratch round
     uint64_t tau_base = ~0ull;               // the threshold ring covers [tau_base, tau_base + kRing)
     bool ring_exact = false;
-    uint64_t win_iters = 0, win_acc = 0;
+    uint32_t win_iters = 0, win_acc = 0;
 
     // hash the buffered accept records (wave 0); the 64-bit sum over lanes is
     // taken in three 22-bit slices so that no slice can carry out
@@ -578,7 +605,7 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
             const uint64_t x0 = (uint32_t)wave_sum((int)(h & 0x3fffff));
             const uint64_t x1 = (uint32_t)wave_sum((int)((h >> 22) & 0x3fffff));
             const uint64_t x2 = (uint32_t)wave_sum((int)(h >> 44));
-            hash += x0 + (x1 << 22) + (x2 << 44);
+            if (tid == 0) hash += x0 + (x1 << 22) + (x2 << 44);
         }
         nrec = 0;
     };
@@ -588,31 +615,37 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
         if (tid == 0) {
             const int16_t pu = L.ps[u], pv = L.ps[v];
             L.ps[u] = pv; L.ps[v] = pu;
-            if (acc_log && accepts < acc_cap) {
+            int64_t* const acc_log = a.acc_log;
+            if (acc_log && accepts < a.acc_cap) {
                 int64_t* e = acc_log + 4 * accepts;
                 e[0] = (int64_t)tt; e[1] = u; e[2] = v; e[3] = d;
             }
             L.rec[nrec] = Rec{tt, ((uint32_t)u << 16) | (uint32_t)v, d};
+            cost += d;
+            accepts += 1;
+            if (cost < best) { best = cost; best_iter = tt + 1; }
         }
-        cost += d;
-        accepts += 1;
         nrec += 1;
-        if (cost < best) { best = cost; best_iter = tt + 1; }
         C.swap_part(u, v);
     };
 
     auto advance = [&](uint32_t k) __attribute__((always_inline)) {   // move the proposal cursor k iterations on
-        t += k;
+        k = uni(k);
+        t = uni64(t + k);
         if (k >= m) k %= m;
         idx0 += k;
         if (idx0 >= m) idx0 -= m;
+        idx0 = uni(idx0);
         if (k < 64) advance_by(n, r0, s0, (int)k);
         else pair_of_u(n, idx0, r0, s0);
+        r0 = uni(r0);
+        s0 = uni(s0);
     };
 
     auto log_tie = [&](uint64_t tt, int d, double z) __attribute__((always_inline)) {
         const unsigned long long slot = atomicAdd(&s_ties, 1ull);
-        if (ties && slot < tie_cap) ties[slot] = qap_near_tie{tt, (int64_t)d, z};
+        qap_near_tie* const ties = a.ties;
+        if (ties && slot < a.tie_cap) ties[slot] = qap_near_tie{tt, (int64_t)d, z};
     };
 
     auto min_key = [&]() __attribute__((always_inline)) -> unsigned long long {
@@ -623,7 +656,7 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
             key = x < key ? x : key;
         }
         buf ^= 1;   // the other set is written next; everyone read this one before the next barrier
-        return key;
+        return uni64(key);
     };
 
     auto refill = [&]() __attribute__((always_inline)) {
@@ -631,13 +664,14 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
         if (tid == 0) s_flag = 0;
         __syncthreads();
         bool ex = false;
+        const uint64_t iters = a.iters;
         for (int i = tid; i < kRing; i += kThreads) {
             const uint64_t tt = tau_base + i;
-            L.tau[i] = tt < iters ? C.threshold(a, tt, &ex) : 0;
+            L.tau[i] = tt < iters ? threshold_at(temps, T0, seed, chain_id, tt, &ex) : 0;
         }
         if (ex) s_flag = 1;
         __syncthreads();
-        ring_exact = s_flag != 0;
+        ring_exact = uni(s_flag) != 0;
         mark(QAP_PH_SCRATCH_THRESH);
         bump(QAP_PH_N_THRESH, 1);
     };
@@ -654,7 +688,7 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
             advance_by(n, r, s, wave * KW);
 #pragma unroll
             for (int i = 0; i < KW; ++i) {
-                pr[i] = r; pc[i] = s;
+                pr[i] = uni(r); pc[i] = uni(s);
                 if (i + 1 < KW) advance_by(n, r, s, 1);
             }
         }
@@ -690,8 +724,7 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
         bool tie = false;
         double zt = 0.0;
         if (valid && dl > 0 && (ring_exact || (dl >= tau - 1 && dl <= tau + 2))) {
-            const uint64_t tw = t + jl;
-            const bool ex = metropolis_positive(dl, temperature(temps, T0, tw), uniform_r(seed, chain_id, tw), &zt);
+            const bool ex = exact_test(dl, temps, T0, seed, chain_id, t + jl, &zt);
             if (ring_exact) acc = ex;
             tie = fabs(zt) < kNearTie;
         }
@@ -714,11 +747,13 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
         } else {
             int u = r0, v = s0;
             advance_by(n, u, v, jstar);
+            u = uni(u);
+            v = uni(v);
             accept_common(t + jstar, u, v, (int)(uint32_t)key);
             __syncthreads();
             if (nrec == kRec) flush();
             advance((uint32_t)jstar + 1);
-            win_iters += jstar + 1;
+            win_iters += (uint32_t)jstar + 1;
             win_acc += 1;
             mark(QAP_PH_SCRATCH_ACCEPT);
             bump(QAP_PH_N_SCRATCH_ACC, 1);
@@ -755,9 +790,8 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
                     if (mine != ~0ull || d == INT_MAX) continue;
                     bool acc = d <= 0;
                     if (!acc && d <= bound) {
-                        const uint64_t tt = t + jv[k];
                         double z;
-                        acc = metropolis_positive(d, temperature(temps, T0, tt), uniform_r(seed, chain_id, tt), &z);
+                        acc = exact_test(d, temps, T0, seed, chain_id, t + jv[k], &z);
                         tie |= fabs(z) < kNearTie;
                     }
                     if (acc) mine = ((unsigned long long)jv[k] << 32) | (uint32_t)d;
@@ -780,10 +814,9 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
                 if (j > limit) break;
                 const int32_t d = L.D[idx];
                 if (d > 0 && d <= bound) {
-                    const uint64_t tt = t + j;
                     double z;
-                    metropolis_positive(d, temperature(temps, T0, tt), uniform_r(seed, chain_id, tt), &z);
-                    if (fabs(z) < kNearTie) log_tie(tt, d, z);
+                    exact_test(d, temps, T0, seed, chain_id, t + j, &z);
+                    if (fabs(z) < kNearTie) log_tie(t + j, d, z);
                 }
                 idx += nt_mod;
                 if (idx >= m) idx -= m;
@@ -794,14 +827,17 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
         bump(QAP_PH_N_SCANNED, jstar == UINT_MAX ? W : jstar + 1);
         if (jstar == UINT_MAX) {
             advance(W);
-            step_e = min(step_e * 2, max_step);
+            step_e = min(step_e * 2, uni(a.max_step));
             return;
         }
         step_e = 1;
         uint32_t istar = idx0 + (jstar % m);
         if (istar >= m) istar -= m;
+        istar = uni(istar);
         int u, v;
         pair_of_u(n, istar, u, v);
+        u = uni(u);
+        v = uni(v);
         const int dstar = (int)(uint32_t)key;
         accept_common(t + jstar, u, v, dstar);
         __syncthreads();
@@ -827,7 +863,8 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
             if (win_iters >= kSwitchWindow) {
                 // few proposals per round while most are accepted, more as acceptance falls
                 kw = win_acc * 4 >= win_iters ? 1 : (win_acc * 16 >= win_iters ? 2 : 4);
-                if (!(flags & kFlagScratchOnly) && win_acc * 1000 < win_iters * (uint64_t)switch_permille) {
+                const uint32_t flags = uni(a.flags), switch_permille = uni(a.switch_permille);
+                if (!(flags & kFlagScratchOnly) && win_acc * 1000u < win_iters * switch_permille) {
                     C.build_delta();
                     mode = 1;
                     step_e = 1;
@@ -848,7 +885,7 @@ __device__ void chain_run(const ChainArgs& a, char* smem)
     // Delta is current in Delta mode; in scratch mode it is rebuilt when the
     // schedule ends and otherwise left stale
     int out_mode = mode == 1 ? QAP_MODE_DELTA : QAP_MODE_SCRATCH_STALE;
-    if (mode == 0 && t >= iters) {
+    if (mode == 0 && t >= a.iters) {
         C.build_delta();
         out_mode = QAP_MODE_SCRATCH;
     }

@@ -356,7 +356,10 @@ class Batch:
         self.descs = None
         self.scratch = {}
 
-    def init(self, ratio: float = 1e-3, flags: int = 0, switch_permille: int = 0):
+    def init(self, ratio: float = 1e-3, flags: int = 0, switch_permille=0):
+        """Step (a) of Sec. 2.2 for every chain and the descriptors of the batch.
+        ``switch_permille`` is a number or a function (n, symmetric) -> number
+        (a tuned table, see tune.py); 0 means the library default."""
         torch = self.torch
         i4, i8, f8 = 4, 8, 8
         for i, ch in enumerate(self.chains):
@@ -385,8 +388,9 @@ class Batch:
                 self.scratch[i] = torch.empty(qap_chain_scratch_bytes(ch.n, inf.symmetric), dtype=torch.uint8,
                                               device=self.p.device)
                 scr = self.scratch[i].data_ptr()
+            sw = switch_permille(ch.n, bool(inf.symmetric)) if callable(switch_permille) else switch_permille
             descs[i] = ChainDesc(ch.n, inf.symmetric, inf.a_min, inf.a_max, inf.b_min, inf.b_max, flags,
-                                 switch_permille, A.data_ptr(), self.Bp.data_ptr() + i4 * bo,
+                                 int(sw), A.data_ptr(), self.Bp.data_ptr() + i4 * bo,
                                  self.p.data_ptr() + i4 * po, self.delta.data_ptr() + i4 * do,
                                  self.state_d[i].data_ptr(), temps, self.ties[i].data_ptr(), self.tie_cap,
                                  ch.chain_id, ch.iters, ch.iters, T0, ch.philox_seed & (2**64 - 1), scr)
@@ -399,6 +403,22 @@ class Batch:
         cfg = BatchConfig(threads, groups, slice_iters, self.prof.data_ptr() if self.prof is not None else None)
         _check(qap_sa_run_batch(self.k, self.descs, self.descs_d, order, cfg, self.ws, stream), "qap_sa_run_batch")
         return self
+
+    def capture(self, slices: int, slice_iters: int, groups: int = 0, order=None):
+        """Record `slices` consecutive slice launches into one HIP graph
+        (torch.cuda.CUDAGraph).  Each replay advances every chain by up to
+        slices * slice_iters iterations from wherever its state stands, so the
+        steady loop costs one graph launch per `slices` slices.  One eager slice
+        must have run first (it sets up the library's side streams)."""
+        torch = self.torch
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(slices):
+                self.run(groups=groups, slice_iters=slice_iters, order=order, stream=s.cuda_stream)
+        torch.cuda.current_stream().wait_stream(s)
+        return g
 
     def states(self) -> list[dict]:
         self.torch.cuda.synchronize()

@@ -1,5 +1,8 @@
 """Batched chains of uneven size in one persistent launch: every chain equals
 the oracle's run of that chain alone, whatever the batch and the slicing."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -15,6 +18,9 @@ def Q():
         pytest.skip("no GPU")
     from paper_1208_2675_amd import qapsa
     return qapsa
+
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_runs.json")
 
 
 def _mix(iters, k_inst=10, per=3, seed=77, n_hi=150):
@@ -67,3 +73,78 @@ def test_batch_alone_equals_mixed(Q):
         alone.run(groups=1)
         assert alone.states()[0] == sm[i]
         assert np.array_equal(alone.perm(0), mixed.perm(i))
+
+
+def test_batch_graph_replays_equal_eager(orc, Q):
+    """The slice loop captured in a HIP graph: every replay leaves the chains
+    where the same number of eager slices does, with eager work and
+    synchronisations between replays, and the finished chains equal the oracle."""
+    import torch
+    chains = _mix(24000, k_inst=6, per=2, seed=80)
+    refs = [_oracle(orc, ch) for ch in chains]
+    eager = Q.Batch(chains).init()
+    graph = Q.Batch(chains).init()
+    si, per = 1000, 3
+    eager.run(slice_iters=si)
+    graph.run(slice_iters=si)
+    g = graph.capture(per, si)
+    reps = 0
+    while not graph.done():
+        for _ in range(per):
+            eager.run(slice_iters=si)
+        g.replay()
+        x = torch.ones(1000, device="cuda").sum()   # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert float(x) == 1000.0
+        assert graph.states() == eager.states(), reps
+        reps += 1
+        assert reps < 20
+    assert eager.done()
+    _check(orc, Q, graph, refs)
+
+
+def test_tuned_thresholds_leave_results_unchanged(orc, Q):
+    """A tuned switch table changes only the time: per-chain thresholds from a
+    short tuning pass give the oracle's results."""
+    from paper_1208_2675_amd import tune
+    table = tune.tune(iters=4000, buckets=((20, 40),), candidates=(5, 500))
+    assert len(table["buckets"]) == 2
+    chains = _mix(12000, k_inst=4, per=2, seed=82)
+    refs = [_oracle(orc, ch) for ch in chains]
+    b = Q.Batch(chains).init(switch_permille=lambda n, sym: tune.switch_for(table, n, sym))
+    b.run()
+    _check(orc, Q, b, refs)
+
+
+def test_every_placement_in_one_batch(orc, Q):
+    """Chains whose state sits wholly in LDS, with Delta in device memory, also
+    with A there, and also with B' there, run side by side (one kernel per
+    placement on forked streams) and each equals the oracle."""
+    chains = []
+    for j, (n, sym) in enumerate([(60, False), (170, False), (230, False), (300, True), (420, True), (90, True)]):
+        A, B = W.sym_uniform(n, (400, j)) if sym else W.asym_sparse_grid(n, (400, j))
+        chains.append(W.Chain(f"pl{j}", A, B, W.random_perm(n, (401, j)), 20000, W.philox_key(402, j), j, sym, {}))
+    kinds = {Q.qap_single_workgroup(ch.n, int(ch.symmetric), 99, 200) for ch in chains}
+    assert kinds == {1, 2}
+    refs = [_oracle(orc, ch) for ch in chains]
+    b = Q.Batch(chains).init()
+    b.run(slice_iters=7000)
+    b.run()
+    _check(orc, Q, b, refs)
+
+
+def test_full_mix_matches_stored_oracle_results(Q):
+    """The 512-chain mix (64 instances, N uniform in [20, 200], I = 1e7 each) in
+    one persistent launch against the oracle's stored full runs, chain by chain."""
+    with open(GOLD) as f:
+        gold = json.load(f)["mix512"]["chains"]
+    chains = W.batched_mix()
+    assert len(chains) == len(gold) == 512
+    b = Q.Batch(chains).init()
+    for i, g in enumerate(gold):
+        assert b.infos[i].sum_abs_delta == g["sum_abs_delta0"] and b.infos[i].cost == g["cost0"], i
+    b.run()
+    for i, (st, g) in enumerate(zip(b.states(), gold)):
+        assert st["t"] == g["t_end"], i
+        for k in ("accepts", "hash", "cost", "best_cost", "best_iter", "near_ties"):
+            assert st[k] == g[k], (i, k, st[k], g[k])
