@@ -35,6 +35,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_chain_dist_update_n2000_traffic.json")
+DIST_SOURCE = os.path.join(ROOT, "paper_1208_2675_amd", "csrc", "qapsa_chain_dist.hip")
+
+
+def source_hash(path: str) -> str:
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(per_update_bytes: int):
+    """HBM bytes per Delta update from the committed counter summary, if it was
+    taken on the current source of the kernel; else None."""
+    if not os.path.exists(TRAFFIC_JSON):
+        return None
+    with open(TRAFFIC_JSON) as f:
+        t = json.load(f)
+    if t.get("source_sha256_16") != source_hash(DIST_SOURCE):
+        return None
+    return {"fetch_bytes_per_update": t["fetch_bytes_per_update"], "write_bytes_per_update": t["write_bytes_per_update"],
+            "bytes_per_update": t["fetch_bytes_per_update"] + t["write_bytes_per_update"],
+            "vs_algorithmic": (t["fetch_bytes_per_update"] + t["write_bytes_per_update"]) / per_update_bytes,
+            "copy_scale": t["copy_scale"], "summary": os.path.relpath(TRAFFIC_JSON, ROOT)}
 
 
 def update_bytes(n: int, symmetric: bool) -> int:
@@ -143,27 +166,46 @@ def section_batched(Q, W, torch, args):
                                 for x in table["buckets"]}}
 
 
+def calibrate_copy(torch, mib: int = 256):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters (run under rocprofv3 --pmc beside the update)."""
+    x = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    return {"copy_bytes": mib << 20}
+
+
 def section_update(Q, W, torch, args):
+    """R equal launches of the multi-workgroup kernel, each making K/R forced
+    accepts (T = +inf) on the N=2000 chain; per-launch durations from HIP
+    events on the stream the kernel runs on."""
     ch = W.single_chain("n2000_sym")
     n = ch.n
-    k = args.update_accepts
-    log(f"update: n={n} forced accepts={k}")
-    c = Q.Chain(ch.A, ch.B, ch.p0, k, ch.philox_seed, ch.chain_id, T0=math.inf)
+    launches = args.update_launches
+    per = args.update_accepts // launches
+    log(f"update: n={n} forced accepts={per * launches} in {launches} launches")
+    c = Q.Chain(ch.A, ch.B, ch.p0, per * launches, ch.philox_seed, ch.chain_id, T0=math.inf)
     c.init()
-    c.run(16)                                   # warm: load, one window
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    c.run(k)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+    ms = []
+    for i in range(launches):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        c.run((i + 1) * per)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms.append(ev0.elapsed_time(ev1))
     st = c.state()
-    ups = (k - 16) / (ms * 1e-3)
-    per = update_bytes(n, True)
-    achieved = per * ups / 1e9
-    return {"n": n, "updates": k - 16, "kernel_ms": ms, "updates_per_s": ups, "us_per_update": 1e6 / ups,
-            "bytes_per_update": per, "achieved_GBs": achieved, "accepts": int(st.accepts), "status": int(st.status)}
+    avg_ms = sum(ms) / len(ms)
+    ups = per / (avg_ms * 1e-3)
+    bytes_per = update_bytes(n, True)
+    achieved = bytes_per * ups / 1e9
+    return {"n": n, "launches": launches, "updates_per_launch": per, "launch_ms": ms, "avg_launch_ms": avg_ms,
+            "updates_per_s": ups, "us_per_update": 1e6 / ups, "bytes_per_update": bytes_per,
+            "bytes_per_launch": bytes_per * per, "achieved_GBs": achieved, "accepts": int(st.accepts),
+            "status": int(st.status)}
 
 
 def section_serve(Q, W, torch, args):
@@ -193,6 +235,7 @@ def main():
     ap.add_argument("--batch-iters", type=int, default=10**7)
     ap.add_argument("--batch-threads", type=int, default=256)
     ap.add_argument("--update-accepts", type=int, default=20_000)
+    ap.add_argument("--update-launches", type=int, default=4)
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-iters", type=int, default=10**7)
     ap.add_argument("--serve-slice", type=int, default=500_000)
@@ -211,6 +254,17 @@ def main():
     from paper_1208_2675_amd import workloads as W
 
     sections = set(args.sections.split(","))
+    if "single" not in sections:   # partial run (profiling): no headline value
+        line = {"metric": "SA iterations/s + Delta-updates/s, 1 GPU: single chain vs batched chains", "value": None,
+                "unit": "iterations/s", "n_gpus": 1, "sections": sorted(sections)}
+        if "update" in sections:
+            line["update_n2000"] = section_update(Q, W, torch, args)
+        if "calib" in sections:
+            line["copy_calibration"] = calibrate_copy(torch)
+        if "batched" in sections:
+            line["batched"] = section_batched(Q, W, torch, args)
+        print(json.dumps(line))
+        return
     s = section_single(Q, W, torch, args)
     ch = s["ch"]
     value = s["iters_total"] / s["wall"]
@@ -242,10 +296,15 @@ def main():
     if "update" in sections:
         u = section_update(Q, W, torch, args)
         line["update_n2000"] = u
+        tr = measured_traffic(u["bytes_per_update"])
         line["roofline"] = {"bound": "hbm", "achieved": u["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": u["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                            "frac": u["achieved_GBs"] / HBM_PEAK_GBS,
+                            "traffic": tr["bytes_per_update"] * u["updates_per_s"] / 1e9 if tr else None,
+                            "traffic_detail": tr,
                             "kernel": "k_chain_dist (N=2000, every proposal accepted)",
-                            "per_unit": f"{u['bytes_per_update']} B per Delta update (int32 algorithmic)"}
+                            "per_unit": f"{u['bytes_per_update']} B per Delta update (int32 algorithmic), "
+                                        f"{u['updates_per_launch']} updates per launch",
+                            "avg_launch_ms": u["avg_launch_ms"]}
     if "serve" in sections:
         line["serve"] = section_serve(Q, W, torch, args)
     if not args.no_cpu_baseline:
