@@ -179,6 +179,7 @@ __device__ __forceinline__ unsigned long long get64(unsigned long long* p)
 }
 
 constexpr int kMaxPerThread = 8;   // n <= 8 * threads
+constexpr int kMaxOwnRows = 64;    // rows per workgroup (n <= 64 G)
 
 // Eq. (2) for Delta > 0 at iteration t, out of line (keeps the FP64 log and the
 // generator from occupying scalar registers across the kernel).
@@ -194,7 +195,8 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     __shared__ unsigned long long s_wkey[16];    // first acceptance per wave of the window
     __shared__ unsigned long long s_key;         // the grid-wide first acceptance
     __shared__ int s_ok;
-    __shared__ int s_self[2];
+    __shared__ int s_selfw[16][2];               // per-wave partial self terms of u, v
+    __shared__ int s_pub[2 * kMaxOwnRows];       // this workgroup's published Delta(r, u), Delta(r, v), row-major
     __shared__ int s_ntie[2];                    // near ties of the window, by window parity
     __shared__ unsigned long long s_tie_j[2][8];
     __shared__ int s_tie_d[2][8];
@@ -222,7 +224,9 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     uint32_t* const lbbp = L_.bbp;
     int16_t* const lps = L_.ps;
     DistWs* ws = a.ws;
-    int* X = a.X;                                 // [2 parities][2 rows][n]
+    // published values, workgroup-major: [2 parities][G workgroups][Rmax own rows][2]
+    int* X = a.X;
+    const int Rmax = (n + G - 1) / G;
 
     const bool prof = a.prof != nullptr && w == 0;
     if (tid < QAP_PHASES) s_prof[tid] = 0;
@@ -283,6 +287,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     const uint64_t seed = a.seed;
     const uint32_t chain_id = a.chain_id;
     const uint64_t spin_limit = a.spin_limit;
+    const bool t0_inf = __builtin_isinf(T0);
     unsigned long long* const slot_base = a.slots;
     uint64_t t = st0.t;
     unsigned long long accepts = st0.accepts, hash = st0.hash, best_iter = st0.best_iter;
@@ -306,7 +311,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     // window also sees them.  Slots alternate by window parity: a workgroup
     // can be at most one window ahead of the slowest.
     auto exchange = [&](bool with_scan) __attribute__((always_inline)) -> unsigned long long {
-        wait_stores();
+        wait_stores();   // the published values of the last update have landed
         __syncthreads();
         epoch += 1;
         const unsigned long long tag = (epoch & 1023ull) << 54;
@@ -368,11 +373,11 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             const int x = which == 0 ? pu : pv, y = which == 0 ? pv : pu;
             if (x % G != w) continue;
             int32_t* row = lD + (x / G) * n;
-            int* src = X + (ppar * 2 + which) * n;
+            const int* src = X + ppar * G * Rmax * 2 + which;
             for (int s = tid; s < n; s += nt) {
                 if (s == x) row[s] = 0;
                 else if (s == y) row[s] = -pd;
-                else row[s] = get(src + s);
+                else row[s] = get((int*)src + ((s % G) * Rmax + s / G) * 2);
             }
         }
         pu = pv = -1;
@@ -385,7 +390,9 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         unsigned long long mine = ~0ull;
         auto test = [&](uint32_t j, int d) __attribute__((always_inline)) {
             bool acc = d <= 0;
-            if (!acc && d <= bound) {
+            if (!acc && t0_inf && inf_draw_clear(seed, chain_id, t + j)) {
+                acc = true;   // T = +inf: accepted, and no near tie (see inf_draw_clear)
+            } else if (!acc && d <= bound) {
                 double z;
                 acc = exact_test(d, temps, T0, seed, chain_id, t + j, &z);
                 if (fabs(z) < kNearTie) {
@@ -492,20 +499,24 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         // B'[v][.] = B[p(u)][p(.)] with p the permutation after the swap.  All
         // global loads are issued before any result is used.
         const int pu_new = uni((int)lps[v]), pv_new = uni((int)lps[u]);
+        const int nk = (n + nt - 1) / nt;   // columns per thread (uniform)
         int ga[kMaxPerThread], gb[kMaxPerThread], gc[kMaxPerThread], gd[kMaxPerThread];
 #pragma unroll
         for (int i = 0; i < kMaxPerThread; ++i) {
-            const int k = tid + i * nt;
-            if (k < n) {
-                const int pk = k == u ? pu_new : (k == v ? pv_new : (int)lps[k]);
-                ga[i] = a.A[u * n + k];
-                gb[i] = a.A[v * n + k];
-                gc[i] = a.B[pu_new * n + pk];
-                gd[i] = a.B[pv_new * n + pk];
-            }
+            if (i >= nk) break;
+            const int k = min(tid + i * nt, n - 1);
+            const int pk = k == u ? pu_new : (k == v ? pv_new : (int)lps[k]);
+            ga[i] = a.A[u * n + k];
+            gb[i] = a.A[v * n + k];
+            gc[i] = a.B[pu_new * n + pk];
+            gd[i] = a.B[pv_new * n + pk];
         }
+        // staged bytes, packed differences and this thread's share of the self
+        // terms <A[x][.], B'[x][.]> of x = u, v
+        int self_u = 0, self_v = 0;
 #pragma unroll
         for (int i = 0; i < kMaxPerThread; ++i) {
+            if (i >= nk) break;
             const int k = tid + i * nt;
             if (k < n) {
                 const int su = ga[i] - a.a_min, sv = gb[i] - a.a_min, tu = gc[i] - a.b_min, tv = gd[i] - a.b_min;
@@ -516,8 +527,13 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 const int da = su - sv, db = tu - tv;
                 labp[k] = (uint32_t)(uint16_t)da | ((uint32_t)(uint16_t)da << 16);
                 lbbp[k] = (uint32_t)(uint16_t)db | ((uint32_t)(uint16_t)db << 16);
+                self_u += su * tu;
+                self_v += sv * tv;
             }
         }
+        self_u = wave_sum(self_u);
+        self_v = wave_sum(self_v);
+        if (lane == 0) { s_selfw[wave][0] = self_u; s_selfw[wave][1] = self_v; }
         __syncthreads();   // staged rows complete; everyone has read p
         if (tid == 0) { lps[u] = (int16_t)pu_new; lps[v] = (int16_t)pv_new; }
         // own rows of B': rows u, v are replaced, the others swap columns u, v
@@ -531,43 +547,53 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 const uint8_t x = row[u]; row[u] = row[v]; row[v] = x;
             }
         }
-        if (wave < 2) {   // self terms <A[x][.], B'[x][.]> of x = u, v
-            const uint32_t* x = (const uint32_t*)(wave == 0 ? lSu : lSv);
-            const uint32_t* y = (const uint32_t*)(wave == 0 ? lTu : lTv);
-            uint32_t acc = 0;
-            for (int k = lane; k < q; k += 64) acc = dot4(x[k], y[k], acc);
-            const int sd = wave_sum((int)acc);
-            if (lane == 0) s_self[wave] = sd;
-        }
         if (nrec == kRec) flush();
         __syncthreads();
 
-        // pairs of own rows disjoint from {u, v}: lanes over columns, rows in turn
+        // pairs of own rows disjoint from {u, v}: for each of this thread's
+        // columns, the entries of up to eight own rows are loaded before any is
+        // stored (a store to Delta may not move above a later load of it, so a
+        // load-update-store loop would wait out one LDS round trip per entry)
         {
-            v2i16 as_[kMaxPerThread], bs_[kMaxPerThread];
+            constexpr int kRowBatch = 8;
+            for (int lr0 = 0; lr0 < Rw; lr0 += kRowBatch) {
+                v2i16 ar[kRowBatch], br[kRowBatch];
+                bool rok[kRowBatch];
+                int rr[kRowBatch];
 #pragma unroll
-            for (int i = 0; i < kMaxPerThread; ++i) {
-                const int s = tid + i * nt;
-                const bool ok = s < n && s != u && s != v;
-                as_[i] = __builtin_bit_cast(v2i16, ok ? labp[s] : 0u);
-                bs_[i] = __builtin_bit_cast(v2i16, ok ? lbbp[s] : 0u);
-            }
-            for (int lr = 0; lr < Rw; ++lr) {
-                const int r = w + G * lr;
-                if (r == u || r == v) continue;
-                const v2i16 ar = __builtin_bit_cast(v2i16, labp[r]), br = __builtin_bit_cast(v2i16, lbbp[r]);
-                int32_t* row = lD + lr * n;
+                for (int h = 0; h < kRowBatch; ++h) {
+                    const int lr = lr0 + h < Rw ? lr0 + h : Rw - 1;
+                    rr[h] = w + G * lr;
+                    rok[h] = lr0 + h < Rw && rr[h] != u && rr[h] != v;
+                    ar[h] = __builtin_bit_cast(v2i16, labp[rr[h]]);
+                    br[h] = __builtin_bit_cast(v2i16, lbbp[rr[h]]);
+                }
 #pragma unroll
                 for (int i = 0; i < kMaxPerThread; ++i) {
+                    if (i * nt >= n) break;
                     const int s = tid + i * nt;
-                    if (s < n && s != u && s != v && s != r)
-                        row[s] = __builtin_amdgcn_sdot2(ar - as_[i], bs_[i] - br, row[s], false);
+                    const bool sok = s < n && s != u && s != v;
+                    const int sc = s < n ? s : 0;
+                    const v2i16 as = __builtin_bit_cast(v2i16, labp[sc]), bs = __builtin_bit_cast(v2i16, lbbp[sc]);
+                    int32_t dv[kRowBatch];
+#pragma unroll
+                    for (int h = 0; h < kRowBatch; ++h) {
+                        const int lr = lr0 + h < Rw ? lr0 + h : Rw - 1;
+                        dv[h] = lD[lr * n + sc];
+                    }
+#pragma unroll
+                    for (int h = 0; h < kRowBatch; ++h)
+                        if (rok[h] && sok && s != rr[h])
+                            lD[(lr0 + h) * n + s] = __builtin_amdgcn_sdot2(ar[h] - as, bs - br[h], dv[h], false);
                 }
             }
         }
         // Delta(r, u), Delta(r, v) of own rows: one wave per row
         {
-            const int su = uni(s_self[0]), sv = uni(s_self[1]);
+            int su = 0, sv = 0;
+        for (int i = 0; i < nwaves; ++i) { su += s_selfw[i][0]; sv += s_selfw[i][1]; }
+        su = uni(su);
+        sv = uni(sv);
             for (int lr = wave; lr < Rw; lr += nwaves) {
                 const int r = w + G * lr;
                 if (r == u || r == v) continue;
@@ -590,10 +616,17 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                     const int dv = finish_sym(Pv - Sr - sv, A_r[r], A_r[v], lSv[r], lSv[v], B_r[r], B_r[v], lTv[r], lTv[v]);
                     lD[lr * n + u] = du;
                     lD[lr * n + v] = dv;
-                    put(X + (par * 2 + 0) * n + r, du);
-                    put(X + (par * 2 + 1) * n + r, dv);
+                    s_pub[2 * lr] = du;
+                    s_pub[2 * lr + 1] = dv;
                 }
             }
+        }
+        // publish this workgroup's touched values as one contiguous block; the
+        // stores complete during the next scan
+        __syncthreads();
+        {
+            int* dst = X + ((par * G + w) * Rmax) * 2;
+            for (int i = tid; i < 2 * Rw; i += nt) put(dst + i, s_pub[i]);
         }
         pu = u; pv = v; pd = dstar; ppar = par;
         par ^= 1;
@@ -666,7 +699,8 @@ int launch_chain_dist(const DistArgs& a0, int G, int threads, hipStream_t stream
     const void* fn = (const void*)k_chain_dist;
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
         return QAP_E_DEVICE;
-    if (G > kMaxGroups || threads > 512 || a.n > kMaxPerThread * threads) return QAP_E_INVAL;
+    if (G > kMaxGroups || threads > 512 || a.n > kMaxPerThread * threads || (a.n + G - 1) / G > kMaxOwnRows)
+        return QAP_E_INVAL;
     hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, stream, a.ws, a.slots);
     void* kargs[] = {&a};
     if (hipLaunchCooperativeKernel(fn, dim3(G), dim3(threads), kargs, (unsigned)bytes, stream) != hipSuccess)

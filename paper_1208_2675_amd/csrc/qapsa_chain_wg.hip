@@ -572,6 +572,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
     const double* __restrict__ temps = a.temps;
     const uint64_t seed = a.seed;
     const uint32_t chain_id = a.chain_id;
+    const bool t0_inf = __builtin_isinf(T0);
 
     const uint32_t nt_mod = (uint32_t)kThreads % m;
     uint64_t t = uni64(st0.t);
@@ -723,7 +724,8 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         bool acc = valid && dl <= tau;
         bool tie = false;
         double zt = 0.0;
-        if (valid && dl > 0 && (ring_exact || (dl >= tau - 1 && dl <= tau + 2))) {
+        if (valid && dl > 0 && (ring_exact || (dl >= tau - 1 && dl <= tau + 2)) &&
+            !(t0_inf && inf_draw_clear(seed, chain_id, t + jl))) {
             const bool ex = exact_test(dl, temps, T0, seed, chain_id, t + jl, &zt);
             if (ring_exact) acc = ex;
             tie = fabs(zt) < kNearTie;
@@ -789,7 +791,9 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
                     const int32_t d = dv[k];
                     if (mine != ~0ull || d == INT_MAX) continue;
                     bool acc = d <= 0;
-                    if (!acc && d <= bound) {
+                    if (!acc && t0_inf && inf_draw_clear(seed, chain_id, t + jv[k])) {
+                        acc = true;   // T = +inf: accepted, and no near tie
+                    } else if (!acc && d <= bound) {
                         double z;
                         acc = exact_test(d, temps, T0, seed, chain_id, t + jv[k], &z);
                         tie |= fabs(z) < kNearTie;

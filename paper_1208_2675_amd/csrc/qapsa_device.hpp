@@ -77,6 +77,19 @@ __device__ __forceinline__ bool metropolis_positive(int64_t delta, double T, dou
 
 constexpr double kNearTie = 1e-12;
 
+// At T = +inf (T0 = +inf makes every T_t infinite) Eq. (2) accepts every
+// Delta > 0 and z = fl(0 + log r) = log r.  A near tie |z| < 1e-12 then needs
+// r > 1 - 1e-12; every draw with u <= 2^52 - 9008, i.e. r <= 1 - 2.0001e-12,
+// is clear of that band whatever the last bit of log, so only draws above
+// it need the FP64 evaluation.
+__device__ __forceinline__ bool inf_draw_clear(uint64_t seed, uint32_t chain, uint64_t t)
+{
+    const uint4 x = philox10(make_uint4((uint32_t)t, (uint32_t)(t >> 32), chain, 0u),
+                             (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint64_t u = ((uint64_t)x.x << 20) | (uint64_t)(x.y >> 12);
+    return u <= (1ull << 52) - 9008ull;
+}
+
 // ------------------------------------------------------------------- hash
 // The trajectory hash is the sum mod 2^64 over accepted swaps of a fingerprint
 // of (t, r, s, Delta); the sum does not depend on the order in which swaps are

@@ -69,11 +69,12 @@ static_assert(sizeof(DistWs) == 64, "workspace header");
 
 // Multi-workgroup exchange area: the header, two sets (by window parity) of
 // one 64-bit slot per workgroup, then the published Delta values (two swap
-// parities x rows u, v x n).
+// parities x G workgroups x ceil(n / G) own rows x {u, v}, at most
+// 2 x 2 x (n + G) ints).
 constexpr int kMaxGroups = 1024;
 inline size_t dist_ws_bytes(int n)
 {
-    return sizeof(DistWs) + 2 * kMaxGroups * sizeof(unsigned long long) + 4 * sizeof(int) * (size_t)n;
+    return sizeof(DistWs) + 2 * kMaxGroups * sizeof(unsigned long long) + 4 * sizeof(int) * ((size_t)n + kMaxGroups);
 }
 inline unsigned long long* dist_slots(void* ws) { return (unsigned long long*)((char*)ws + sizeof(DistWs)); }
 inline int* dist_X(void* ws) { return (int*)(dist_slots(ws) + 2 * kMaxGroups); }
