@@ -552,27 +552,26 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
 
         // pairs of own rows disjoint from {u, v}: for each of this thread's
         // columns, the entries of up to eight own rows are loaded before any is
-        // stored (a store to Delta may not move above a later load of it, so a
-        // load-update-store loop would wait out one LDS round trip per entry)
+        // stored (a store to Delta may not move above a later load of it).
+        // Entries in columns u, v and in rows u, v get a meaningless value:
+        // the first are rewritten below (after a barrier), the rows are stale
+        // and refreshed from the published values, and the diagonal is never
+        // read.  So the only mask is the end of the row.
         {
             constexpr int kRowBatch = 8;
             for (int lr0 = 0; lr0 < Rw; lr0 += kRowBatch) {
                 v2i16 ar[kRowBatch], br[kRowBatch];
-                bool rok[kRowBatch];
-                int rr[kRowBatch];
 #pragma unroll
                 for (int h = 0; h < kRowBatch; ++h) {
                     const int lr = lr0 + h < Rw ? lr0 + h : Rw - 1;
-                    rr[h] = w + G * lr;
-                    rok[h] = lr0 + h < Rw && rr[h] != u && rr[h] != v;
-                    ar[h] = __builtin_bit_cast(v2i16, labp[rr[h]]);
-                    br[h] = __builtin_bit_cast(v2i16, lbbp[rr[h]]);
+                    const int r = w + G * lr;
+                    ar[h] = __builtin_bit_cast(v2i16, labp[r]);
+                    br[h] = __builtin_bit_cast(v2i16, lbbp[r]);
                 }
 #pragma unroll
                 for (int i = 0; i < kMaxPerThread; ++i) {
                     if (i * nt >= n) break;
                     const int s = tid + i * nt;
-                    const bool sok = s < n && s != u && s != v;
                     const int sc = s < n ? s : 0;
                     const v2i16 as = __builtin_bit_cast(v2i16, labp[sc]), bs = __builtin_bit_cast(v2i16, lbbp[sc]);
                     int32_t dv[kRowBatch];
@@ -581,13 +580,16 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                         const int lr = lr0 + h < Rw ? lr0 + h : Rw - 1;
                         dv[h] = lD[lr * n + sc];
                     }
+                    if (s < n) {
 #pragma unroll
-                    for (int h = 0; h < kRowBatch; ++h)
-                        if (rok[h] && sok && s != rr[h])
-                            lD[(lr0 + h) * n + s] = __builtin_amdgcn_sdot2(ar[h] - as, bs - br[h], dv[h], false);
+                        for (int h = 0; h < kRowBatch; ++h)
+                            if (lr0 + h < Rw)
+                                lD[(lr0 + h) * n + s] = __builtin_amdgcn_sdot2(ar[h] - as, bs - br[h], dv[h], false);
+                    }
                 }
             }
         }
+        __syncthreads();   // columns u, v of own rows are written next
         // Delta(r, u), Delta(r, v) of own rows: one wave per row
         {
             int su = 0, sv = 0;

@@ -394,20 +394,61 @@ struct Chain {
     }
 
     // Pairs disjoint from {u, v}: the O(1) correction of Sec. 3 (i) from the
-    // staged vectors.  Wave w takes rows r = w mod 4, lanes run along the row.
-    __device__ void taillard(int u, int v) const
+    // staged vectors.  Lanes own columns s (blocks of 64); an item is eight
+    // rows r < s of one block, items go round-robin to the waves, and an
+    // item's loads all precede its stores (a store to Delta may not move above
+    // a later load of it).  Pairs that meet {u, v} are updated too, with a
+    // meaningless value: finish_rows rewrites all of them after the next
+    // barrier, and skipping them would cost a mask per entry.  A wave issues
+    // one instruction per four cycles whatever its kind, so items wholly below
+    // the diagonal take a path without masks or per-entry index arithmetic.
+    __device__ void taillard() const
     {
-        for (int r = wave; r < n - 1; r += kWaves) {
-            if (r == u || r == v) continue;
-            const v2i16 ar = __builtin_bit_cast(v2i16, L.abp[r]);
-            const v2i16 br = __builtin_bit_cast(v2i16, L.bbp[r]);
-            const uint32_t base = rs32(n, r) - (uint32_t)r - 1u;   // + s: entry (r, s)
-            for (int s = r + 1 + lane; s < n; s += 64) {
-                if (s == u || s == v) continue;
-                const v2i16 as = __builtin_bit_cast(v2i16, L.abp[s]);
-                const v2i16 bs = __builtin_bit_cast(v2i16, L.bbp[s]);
-                int32_t* e = L.D + (base + (uint32_t)s);
-                *e = __builtin_amdgcn_sdot2(ar - as, bs - br, *e, false);
+        constexpr int RB = 8;
+        int item = 0;
+        for (int b = 0; (b << 6) < n; ++b) {
+            const int s = (b << 6) + lane;
+            const int sc = s < n ? s : n - 1;
+            const v2i16 as = __builtin_bit_cast(v2i16, L.abp[sc]), bs = __builtin_bit_cast(v2i16, L.bbp[sc]);
+            const int rlim = min(n - 1, (b << 6) + 63);   // rows below some column of the block
+            const bool full_cols = (b << 6) + 64 <= n;
+            for (int r0 = 0; r0 < rlim; r0 += RB, ++item) {
+                if ((item & (kWaves - 1)) != wave) continue;
+                uint32_t base = rs32(n, r0) - (uint32_t)r0 - 1u;   // + s: entry (r0, s)
+                if (full_cols && r0 + RB <= (b << 6)) {
+                    int32_t dv[RB];
+                    uint32_t off[RB];
+                    v2i16 ar[RB], br[RB];
+#pragma unroll
+                    for (int h = 0; h < RB; ++h) {
+                        ar[h] = __builtin_bit_cast(v2i16, L.abp[r0 + h]);
+                        br[h] = __builtin_bit_cast(v2i16, L.bbp[r0 + h]);
+                        off[h] = base + (uint32_t)s;
+                        dv[h] = L.D[off[h]];
+                        base += (uint32_t)(n - (r0 + h) - 2);      // next row's offset
+                    }
+#pragma unroll
+                    for (int h = 0; h < RB; ++h)
+                        L.D[off[h]] = __builtin_amdgcn_sdot2(ar[h] - as, bs - br[h], dv[h], false);
+                } else {
+                    int32_t dv[RB];
+                    uint32_t off[RB];
+                    v2i16 ar[RB], br[RB];
+                    bool ok[RB];
+#pragma unroll
+                    for (int h = 0; h < RB; ++h) {
+                        const int r = r0 + h;
+                        const int rc = r < rlim ? r : r0;
+                        ok[h] = s < n && r < rlim && s > r;
+                        ar[h] = __builtin_bit_cast(v2i16, L.abp[rc]);
+                        br[h] = __builtin_bit_cast(v2i16, L.bbp[rc]);
+                        off[h] = rs32(n, rc) - (uint32_t)rc - 1u + (uint32_t)(ok[h] ? s : rc + 1);
+                        dv[h] = L.D[off[h]];
+                    }
+#pragma unroll
+                    for (int h = 0; h < RB; ++h)
+                        if (ok[h]) L.D[off[h]] = __builtin_amdgcn_sdot2(ar[h] - as, bs - br[h], dv[h], false);
+                }
             }
         }
     }
@@ -848,7 +889,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         C.stage(u, v);
         if (nrec == kRec) flush();
         __syncthreads();
-        C.taillard(u, v);
+        C.taillard();
         C.gemv_part(u, v);
         __syncthreads();
         C.finish_rows(u, v, false);
