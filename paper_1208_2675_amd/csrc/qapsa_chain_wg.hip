@@ -66,8 +66,8 @@ struct Wg {
     uint8_t* Bb;   // B' - b_min
     uint8_t* Bt;   // (B' - b_min)^T            (asymmetric only)
     int32_t* D;    // packed Delta
-    uint32_t* abp; // staged (A[k][u]-A[k][v], A[u][k]-A[v][k]) as int16 pairs
-    uint32_t* bbp; // staged (B'[k][u]-B'[k][v], B'[u][k]-B'[v][k])
+    uint2* stg;    // staged, as int16 pairs: .x (A[k][u]-A[k][v], A[u][k]-A[v][k]),
+                   // .y (B'[k][u]-B'[k][v], B'[u][k]-B'[v][k])
     int32_t* part; // [2][kWaves][n] per-wave partial sums of the pairs (u, s) and (v, s)
     int32_t* tau;  // ring of acceptance thresholds
     int16_t* ps;   // p
@@ -94,15 +94,14 @@ __host__ __device__ inline size_t wg_layout(int n, int q, bool sym, int place, c
     char* bb = place >= 3 ? gtake(n * P) : take(n * P);
     char* bt = sym ? nullptr : (place >= 3 ? gtake(n * P) : take(n * P));
     char* d = place >= 1 ? (char*)gdelta : take(4 * m);
-    char* abp = take(4 * (size_t)n);
-    char* bbp = take(4 * (size_t)n);
+    char* stg = take(8 * (size_t)n);
     char* part = take(4 * 2 * (size_t)kWaves * n);
     char* tau = take(4 * (size_t)kRing);
     char* ps = take(2 * (size_t)n);
     char* rec = take(sizeof(Rec) * kRec);
     if (L) {
         L->Ab = (uint8_t*)ab; L->At = (uint8_t*)at; L->Bb = (uint8_t*)bb; L->Bt = (uint8_t*)bt;
-        L->D = (int32_t*)d; L->abp = (uint32_t*)abp; L->bbp = (uint32_t*)bbp; L->part = (int32_t*)part;
+        L->D = (int32_t*)d; L->stg = (uint2*)stg; L->part = (int32_t*)part;
         L->tau = (int32_t*)tau; L->ps = (int16_t*)ps; L->rec = (Rec*)rec;
     }
     return off;
@@ -388,68 +387,68 @@ struct Chain {
                 b1 = L.Bt[u * P + k] - L.Bt[v * P + k];
                 b2 = Be(u, k) - Be(v, k);
             }
-            L.abp[k] = (uint32_t)(uint16_t)a1 | ((uint32_t)(uint16_t)a2 << 16);
-            L.bbp[k] = (uint32_t)(uint16_t)b1 | ((uint32_t)(uint16_t)b2 << 16);
+            L.stg[k] = make_uint2((uint32_t)(uint16_t)a1 | ((uint32_t)(uint16_t)a2 << 16),
+                                  (uint32_t)(uint16_t)b1 | ((uint32_t)(uint16_t)b2 << 16));
         }
     }
 
     // Pairs disjoint from {u, v}: the O(1) correction of Sec. 3 (i) from the
-    // staged vectors.  Lanes own columns s (blocks of 64); an item is eight
-    // rows r < s of one block, items go round-robin to the waves, and an
-    // item's loads all precede its stores (a store to Delta may not move above
-    // a later load of it).  Pairs that meet {u, v} are updated too, with a
-    // meaningless value: finish_rows rewrites all of them after the next
-    // barrier, and skipping them would cost a mask per entry.  A wave issues
-    // one instruction per four cycles whatever its kind, so items wholly below
-    // the diagonal take a path without masks or per-entry index arithmetic.
+    // staged vectors.  The packed triangle is folded into a rectangle n wide:
+    // folded row f holds row f of the triangle in columns c < n-1-f (the pair
+    // (f, f+1+c)) and row n-2-f after it (the pair (n-2-f, c)).  Read in
+    // order and cut after the M = n(n-1)/2 entries, the rectangle covers every
+    // pair once (for even n the middle row would otherwise come twice).  Lanes
+    // take its entries in order, 64 to a wave and 256 to a step, carrying
+    // (f, c) from step to step, so that every lane of every step but the last
+    // does useful work whatever n is.  Four steps are loaded before any is
+    // stored (a store to Delta may not move above a later load of it).  Pairs
+    // that meet {u, v} are updated too, with a meaningless value:
+    // finish_rows rewrites all of them after the next barrier, and skipping
+    // them would cost a mask per entry.
     __device__ void taillard() const
     {
-        constexpr int RB = 8;
-        int item = 0;
-        for (int b = 0; (b << 6) < n; ++b) {
-            const int s = (b << 6) + lane;
-            const int sc = s < n ? s : n - 1;
-            const v2i16 as = __builtin_bit_cast(v2i16, L.abp[sc]), bs = __builtin_bit_cast(v2i16, L.bbp[sc]);
-            const int rlim = min(n - 1, (b << 6) + 63);   // rows below some column of the block
-            const bool full_cols = (b << 6) + 64 <= n;
-            for (int r0 = 0; r0 < rlim; r0 += RB, ++item) {
-                if ((item & (kWaves - 1)) != wave) continue;
-                uint32_t base = rs32(n, r0) - (uint32_t)r0 - 1u;   // + s: entry (r0, s)
-                if (full_cols && r0 + RB <= (b << 6)) {
-                    int32_t dv[RB];
-                    uint32_t off[RB];
-                    v2i16 ar[RB], br[RB];
+        constexpr int kStep = 64 * kWaves, U = 4;
+        const uint32_t m = __umul24((uint32_t)n, (uint32_t)(n - 1)) >> 1;
+        const int fq = kStep / n, cq = kStep - fq * n;     // one step, as folded rows and columns
+        int f = 0, c = wave * 64 + lane;
+        while (c >= n) { c -= n; ++f; }                    // at most 255 / n + 1 times
+        auto next = [&]() __attribute__((always_inline)) {
+            f += fq;
+            c += cq;
+            if (c >= n) { c -= n; ++f; }
+        };
+        // entry (f, c) of the folded rectangle: Delta offset and the pair's staged differences
+        auto locate = [&](uint32_t& off, v2i16& x, v2i16& y) __attribute__((always_inline)) {
+            const bool first = c < n - 1 - f;
+            const int r = first ? f : n - 2 - f;
+            const int s = first ? f + 1 + c : c;
+            off = (__umul24((uint32_t)r, (uint32_t)(2 * n - 1 - r)) >> 1) + (uint32_t)(s - r - 1);
+            const uint2 gr = L.stg[r], gs = L.stg[s];
+            x = __builtin_bit_cast(v2i16, gr.x) - __builtin_bit_cast(v2i16, gs.x);
+            y = __builtin_bit_cast(v2i16, gs.y) - __builtin_bit_cast(v2i16, gr.y);
+        };
+        uint32_t kb = (uint32_t)(wave * 64);                // this wave's first entry of the step
+        for (; kb + (U - 1) * kStep + 64 <= m; kb += U * kStep) {
+            uint32_t off[U];
+            int32_t dv[U];
+            v2i16 x[U], y[U];
 #pragma unroll
-                    for (int h = 0; h < RB; ++h) {
-                        ar[h] = __builtin_bit_cast(v2i16, L.abp[r0 + h]);
-                        br[h] = __builtin_bit_cast(v2i16, L.bbp[r0 + h]);
-                        off[h] = base + (uint32_t)s;
-                        dv[h] = L.D[off[h]];
-                        base += (uint32_t)(n - (r0 + h) - 2);      // next row's offset
-                    }
-#pragma unroll
-                    for (int h = 0; h < RB; ++h)
-                        L.D[off[h]] = __builtin_amdgcn_sdot2(ar[h] - as, bs - br[h], dv[h], false);
-                } else {
-                    int32_t dv[RB];
-                    uint32_t off[RB];
-                    v2i16 ar[RB], br[RB];
-                    bool ok[RB];
-#pragma unroll
-                    for (int h = 0; h < RB; ++h) {
-                        const int r = r0 + h;
-                        const int rc = r < rlim ? r : r0;
-                        ok[h] = s < n && r < rlim && s > r;
-                        ar[h] = __builtin_bit_cast(v2i16, L.abp[rc]);
-                        br[h] = __builtin_bit_cast(v2i16, L.bbp[rc]);
-                        off[h] = rs32(n, rc) - (uint32_t)rc - 1u + (uint32_t)(ok[h] ? s : rc + 1);
-                        dv[h] = L.D[off[h]];
-                    }
-#pragma unroll
-                    for (int h = 0; h < RB; ++h)
-                        if (ok[h]) L.D[off[h]] = __builtin_amdgcn_sdot2(ar[h] - as, bs - br[h], dv[h], false);
-                }
+            for (int j = 0; j < U; ++j) {
+                locate(off[j], x[j], y[j]);
+                dv[j] = L.D[off[j]];
+                next();
             }
+#pragma unroll
+            for (int j = 0; j < U; ++j) L.D[off[j]] = __builtin_amdgcn_sdot2(x[j], y[j], dv[j], false);
+        }
+        for (; kb < m; kb += kStep) {
+            if (kb + (uint32_t)lane < m) {
+                uint32_t off;
+                v2i16 x, y;
+                locate(off, x, y);
+                L.D[off] = __builtin_amdgcn_sdot2(x, y, L.D[off], false);
+            }
+            next();
         }
     }
 
