@@ -86,6 +86,13 @@ def lib():
                                  C.c_uint64, C.c_uint32,
                                  C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_uint64]
         L.orc_sa_run.restype = C.c_int
+        L.orc_sa_run_order.argtypes = [C.c_int32, i32p, i32p, i32p, C.POINTER(State),
+                                       C.c_uint64, C.c_uint64, C.c_double, C.c_double,
+                                       C.c_uint64, C.c_uint32, C.c_int32,
+                                       C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_uint64]
+        L.orc_sa_run_order.restype = C.c_int
+        L.orc_random_pair_index.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64]
+        L.orc_random_pair_index.restype = C.c_uint64
         L.orc_brute_force.argtypes = [C.c_int32, i32p, i32p, i32p, C.POINTER(C.c_uint64)]
         L.orc_brute_force.restype = C.c_int64
         _lib = L
@@ -178,11 +185,17 @@ def schedule(A, B, p, iters: int, ratio: float = 1e-3) -> dict:
     return {"T0": T0, "alpha": geometric_alpha(iters, ratio), "iters": int(iters), "sum_abs": sabs}
 
 
+def random_pair_index(seed: int, chain: int, t: int, m: int) -> int:
+    """Pair number proposed at iteration t under random order."""
+    return int(lib().orc_random_pair_index(seed, chain, t, m))
+
+
 def sa_run(A, B, p0, iters: int, T0: float, alpha: float, seed: int, chain: int = 0,
            t_end: int | None = None, state: State | None = None, acc_cap: int = 0,
-           tie_cap: int = 64) -> dict:
+           tie_cap: int = 64, order: int = 0) -> dict:
     """Steps (b)-(e) of the Delta-matrix approach as a from-scratch SA run over
-    iterations [state.t, t_end).  Returns the final p, the state and the logs."""
+    iterations [state.t, t_end); order 0 proposes the pairs in row-major order,
+    order 1 at random.  Returns the final p, the state and the logs."""
     A, B = _mats(A, B)
     n = A.shape[0]
     p = np.ascontiguousarray(p0, dtype=np.int32).copy()
@@ -194,9 +207,9 @@ def sa_run(A, B, p0, iters: int, T0: float, alpha: float, seed: int, chain: int 
     acc = np.zeros((max(acc_cap, 1), 4), dtype=np.int64)
     tie_t = np.zeros(max(tie_cap, 1), dtype=np.uint64)
     tie_z = np.zeros(max(tie_cap, 1), dtype=np.float64)
-    rc = L.orc_sa_run(n, A, B, p, C.byref(state), iters, t_end, T0, alpha, seed, chain,
-                      acc.ctypes.data if acc_cap else None, acc_cap,
-                      tie_t.ctypes.data, tie_z.ctypes.data, tie_cap)
+    rc = L.orc_sa_run_order(n, A, B, p, C.byref(state), iters, t_end, T0, alpha, seed, chain, order,
+                            acc.ctypes.data if acc_cap else None, acc_cap,
+                            tie_t.ctypes.data, tie_z.ctypes.data, tie_cap)
     if rc != 0:
         raise ValueError(f"orc_sa_run failed with status {rc}")
     nacc = min(state.accepts, acc_cap)

@@ -35,6 +35,11 @@
  *                                of Eq. (2); every proposal's cost is recomputed
  *                                from scratch, so the trajectory does not depend on
  *                                any maintained Delta matrix.
+ *   orc_random_pair_index /
+ *   orc_sa_run_order             the same run with the pairs drawn at random
+ *                                (Sec. 2.1 lets the next swap be chosen randomly
+ *                                or sequentially): iteration t proposes a pair
+ *                                drawn from its own counter (reading below).
  *   orc_brute_force              the exact optimum over all N! permutations (N <= 10).
  *
  * Readings where the paper is silent (each is also listed in the design notes):
@@ -48,6 +53,10 @@
  *   - r_t = (2 u + 1) 2^-53 with u the 52 bits (x0 << 20) | (x1 >> 12) of the
  *     generator output for counter (lo32 t, hi32 t, chain, 0), key (lo32 seed,
  *     hi32 seed); exact in binary64 and strictly inside (0, 1).
+ *   - Random order: iteration t proposes pair number floor(x2 M / 2^32) of the
+ *     row-major enumeration (M = n(n-1)/2), x2 being the third output word of
+ *     the same generator call that gives r_t.  Each of the M pairs takes
+ *     floor(2^32 / M) or that plus one of the 2^32 values of x2.
  *   - T_t = ((T0 * H[t >> 20]) * M[(t >> 10) & 1023]) * L[t & 1023] with
  *     L[j] = L[j-1] alpha, M[j] = M[j-1] (L[1023] alpha),
  *     H[j] = H[j-1] (M[1023] L[1023] alpha), all three starting at 1.
@@ -201,6 +210,16 @@ double orc_uniform(uint64_t seed, uint32_t chain, uint64_t t)
     return (double)(2 * u + 1) * 0x1p-53;
 }
 
+/* Pair number proposed at iteration t under random order (m = n(n-1)/2 pairs). */
+uint64_t orc_random_pair_index(uint64_t seed, uint32_t chain, uint64_t t, uint64_t m)
+{
+    const uint32_t ctr[4] = {(uint32_t)t, (uint32_t)(t >> 32), chain, 0u};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    return ((uint64_t)x[2] * m) >> 32;
+}
+
 /* ------------------------------------------------------------ cooling schedule */
 
 /* alpha of a geometric schedule that falls by `ratio` over `iters` iterations. */
@@ -296,23 +315,34 @@ static int orc_is_perm(int32_t n, const int32_t *p)
     return ok;
 }
 
+/* (r, s) of pair number idx in row-major r < s order. */
+static void orc_pair_of_index(int32_t n, uint64_t idx, int32_t *r, int32_t *s)
+{
+    int32_t row = 0;
+    while (idx >= (uint64_t)(n - 1 - row)) { idx -= (uint64_t)(n - 1 - row); ++row; }
+    *r = row;
+    *s = row + 1 + (int32_t)idx;
+}
+
 /*
  * Iterations st->t .. t_end-1 of an SA run of length `iters` (Sec. 2.1-2.2).
- * Iteration t proposes pair number (t mod n(n-1)/2) in row-major r < s order,
- * computes its swap cost from scratch, applies Eq. (2) with T_t and r_t, and on
- * acceptance swaps p(r), p(s) and adds the swap cost to the tracked cost.
+ * Iteration t proposes a pair (r, s), computes its swap cost from scratch,
+ * applies Eq. (2) with T_t and r_t, and on acceptance swaps p(r), p(s) and adds
+ * the swap cost to the tracked cost.  order 0: pair number (t mod n(n-1)/2) in
+ * row-major r < s order.  order 1: pair number orc_random_pair_index(t).
  *
  * acc_log (optional): 4 int64 per accepted swap (t, r, s, delta), the first
  *   acc_cap of them counted from st->accepts == 0.
  * tie_t / tie_z (optional): the first tie_cap near ties (|z| < 1e-12): t and z.
  */
-int orc_sa_run(int32_t n, const int32_t *A, const int32_t *B, int32_t *p, orc_state *st,
-               uint64_t iters, uint64_t t_end, double T0, double alpha,
-               uint64_t seed, uint32_t chain,
-               int64_t *acc_log, uint64_t acc_cap,
-               uint64_t *tie_t, double *tie_z, uint64_t tie_cap)
+int orc_sa_run_order(int32_t n, const int32_t *A, const int32_t *B, int32_t *p, orc_state *st,
+                     uint64_t iters, uint64_t t_end, double T0, double alpha,
+                     uint64_t seed, uint32_t chain, int32_t order,
+                     int64_t *acc_log, uint64_t acc_cap,
+                     uint64_t *tie_t, double *tie_z, uint64_t tie_cap)
 {
-    if (n < 2 || t_end > iters || st->t > t_end || !(T0 > 0.0) || !(alpha > 0.0) || alpha > 1.0)
+    if (n < 2 || t_end > iters || st->t > t_end || !(T0 > 0.0) || !(alpha > 0.0) || alpha > 1.0 ||
+        (order != 0 && order != 1))
         return ORC_E_INVAL;
     if (!orc_is_perm(n, p)) return ORC_E_NOT_PERM;
     if (orc_check_bounds(n, A, B) != ORC_OK) return ORC_E_RANGE;
@@ -325,13 +355,12 @@ int orc_sa_run(int32_t n, const int32_t *A, const int32_t *B, int32_t *p, orc_st
     if (!L || !M || !H) { free(L); free(M); free(H); return ORC_E_INVAL; }
     orc_temperature_tables(alpha, iters, L, M, H);
 
-    /* the pair proposed at iteration st->t */
-    uint64_t idx = st->t % m;
-    int32_t r = 0;
-    while (idx >= (uint64_t)(n - 1 - r)) { idx -= (uint64_t)(n - 1 - r); ++r; }
-    int32_t s = r + 1 + (int32_t)idx;
+    /* the pair proposed at iteration st->t in row-major order */
+    int32_t r, s;
+    orc_pair_of_index(n, st->t % m, &r, &s);
 
     for (uint64_t t = st->t; t < t_end; ++t) {
+        if (order == 1) orc_pair_of_index(n, orc_random_pair_index(seed, chain, t, m), &r, &s);
         const int64_t delta = orc_swap_cost(n, A, B, p, r, s);
         int accept;
         if (delta <= 0) {
@@ -375,6 +404,17 @@ int orc_sa_run(int32_t n, const int32_t *A, const int32_t *B, int32_t *p, orc_st
     st->t = t_end;
     free(L); free(M); free(H);
     return ORC_OK;
+}
+
+/* The row-major run (order 0). */
+int orc_sa_run(int32_t n, const int32_t *A, const int32_t *B, int32_t *p, orc_state *st,
+               uint64_t iters, uint64_t t_end, double T0, double alpha,
+               uint64_t seed, uint32_t chain,
+               int64_t *acc_log, uint64_t acc_cap,
+               uint64_t *tie_t, double *tie_z, uint64_t tie_cap)
+{
+    return orc_sa_run_order(n, A, B, p, st, iters, t_end, T0, alpha, seed, chain, 0,
+                            acc_log, acc_cap, tie_t, tie_z, tie_cap);
 }
 
 /* ------------------------------------------------------------ brute force */
