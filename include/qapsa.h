@@ -132,6 +132,12 @@ typedef struct {
 #define QAP_FLAG_MULTI_WG 4u      /* symmetric byte-valued instances: run on the multi-workgroup
                                      kernel even where one workgroup could hold the chain
                                      (qap_sa_run only; the result is the same)                */
+#define QAP_FLAG_RANDOM_ORDER 8u  /* propose the pairs at random instead of in row-major order
+                                     (Sec. 2.1): iteration t proposes pair number
+                                     floor(x2 M / 2^32) of the row-major enumeration, x2 the
+                                     third output word of the generator call that gives r_t.
+                                     A different run from the default order; resumed slices
+                                     must keep the flag                                       */
 
 /* Device buffers a run reads or appends to (host struct of device pointers). */
 typedef struct {

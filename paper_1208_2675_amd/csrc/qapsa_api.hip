@@ -21,7 +21,8 @@ int check_schedule(const qap_schedule* s)
     if (s->iters == 0 || s->t_end > s->iters) return QAP_E_INVAL;
     if (!(s->T0 > 0.0)) return QAP_E_INVAL;                // rejects NaN and <= 0; +inf allowed
     if (!(s->alpha > 0.0) || s->alpha > 1.0) return QAP_E_INVAL;
-    if ((s->flags & ~(QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY | QAP_FLAG_MULTI_WG)) != 0) return QAP_E_INVAL;
+    if ((s->flags & ~(QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY | QAP_FLAG_MULTI_WG | QAP_FLAG_RANDOM_ORDER)) != 0)
+        return QAP_E_INVAL;
     if ((s->flags & QAP_FLAG_DELTA_ONLY) && (s->flags & QAP_FLAG_SCRATCH_ONLY)) return QAP_E_INVAL;
     if (s->switch_permille > 1000 || s->reserved != 0) return QAP_E_INVAL;
     return QAP_OK;
@@ -174,7 +175,9 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
             d.n = n;
             d.a_min = info->a_min;
             d.b_min = info->b_min;
-            d.kmin = 4096;
+            d.random_order = (sched->flags & QAP_FLAG_RANDOM_ORDER) ? 1u : 0u;
+            // a random-order window is drawn whole by every workgroup: start it small
+            d.kmin = d.random_order ? 512 : 4096;
             d.kmax = (1u << 22) - 2;   // window offsets fit the 22-bit field of an exchange slot
             d.spin_limit = 1ull << 22;
             d.A = A; d.B = B; d.Bp = Bp; d.p = p; d.delta = delta; d.state = state;
@@ -226,7 +229,8 @@ QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,
         const qap_chain_desc& d = host_descs[i];
         if (d.n < 2 || d.n > 46340 || !d.A || !d.Bp || !d.p || !d.delta || !d.state || !d.temps) return QAP_E_INVAL;
         if (d.iters == 0 || d.t_end > d.iters || !(d.T0 > 0.0)) return QAP_E_INVAL;
-        if ((d.flags & ~(QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY)) != 0 || d.switch_permille > 1000)
+        if ((d.flags & ~(QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY | QAP_FLAG_RANDOM_ORDER)) != 0 ||
+            d.switch_permille > 1000)
             return QAP_E_INVAL;
         if ((int64_t)d.a_max - d.a_min > 255 || (int64_t)d.b_max - d.b_min > 255) return QAP_E_UNSUPPORTED;
         const int place = wg_place(d.n, d.symmetric != 0);

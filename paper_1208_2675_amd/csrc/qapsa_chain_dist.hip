@@ -288,6 +288,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     const uint32_t chain_id = a.chain_id;
     const uint64_t spin_limit = a.spin_limit;
     const bool t0_inf = __builtin_isinf(T0);
+    const bool rnd = a.random_order != 0;
     unsigned long long* const slot_base = a.slots;
     uint64_t t = st0.t;
     unsigned long long accepts = st0.accepts, hash = st0.hash, best_iter = st0.best_iter;
@@ -406,10 +407,27 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             }
         };
         __syncthreads();   // the last update's LDS writes are visible
+        if (rnd) {
+            // random order: every workgroup draws the whole window and tests the
+            // proposals it holds -- (r, s) from row s, or from row r where row s
+            // is stale -- so that each proposal is tested exactly once
+            for (uint32_t j = tid; j < W; j += nt) {
+                int r, s;
+                pair_of_u(n, random_pair_index(seed, chain_id, t + j, m), r, s);
+                const bool s_stale = s == pu || s == pv;
+                if (!s_stale) {
+                    if (s % G == w) test(j, lD[(s / G) * n + r]);
+                } else if (r == pu && s == pv) {
+                    if (s % G == w) test(j, -pd);
+                } else if (r != pu && r != pv && r % G == w) {
+                    test(j, lD[(r / G) * n + s]);
+                }
+            }
+        }
         // proposals (r, s) with s owned here, r < s, in the window.  The rows of
         // the window are r0, r0 + 1, ... cyclically; row offset n - 1 is row r0
         // again, for a window that wraps round to the pairs before (r0, s0).
-        if (C > 0) {
+        if (!rnd && C > 0) {
             const int rows_per_pass = max(1, nt / C);
             const int i_loc = tid / C, c = tid - i_loc * C;
             const int s = w + G * c;
@@ -433,7 +451,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             }
         }
         // proposals (r, x) with x a stale row and r owned here: read from row r
-        if (pu >= 0) {
+        if (!rnd && pu >= 0) {
             for (int lr = tid; lr < 2 * Rw; lr += nt) {
                 const int rr = w + G * (lr >> 1), x = (lr & 1) ? pv : pu;
                 if (rr == pu || rr == pv || x <= rr) continue;
@@ -479,6 +497,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         const uint64_t tstar = t + jstar;
         uint32_t istar = idx0 + jstar;
         if (istar >= m) istar -= m;
+        if (rnd) istar = random_pair_index(seed, chain_id, tstar, m);
         istar = uni(istar);
         int u, v;
         pair_of_u(n, istar, u, v);

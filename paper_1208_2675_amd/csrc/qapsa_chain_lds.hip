@@ -112,6 +112,11 @@ __device__ void chain_body(const ChainArgs& a, char* smem)
     const uint32_t nt_mod = (uint32_t)nt % m;
     uint64_t t = s_t;
     uint32_t idx0 = (uint32_t)(t % m);
+    const bool rnd = (a.flags & QAP_FLAG_RANDOM_ORDER) != 0;
+    // pair number proposed at iteration t + j; idx is that of the row-major cursor
+    auto pair_at = [&](uint32_t j, uint32_t idx) -> uint32_t {
+        return rnd ? random_pair_index(a.seed, a.chain_id, t + j, m) : idx;
+    };
     int step_e = 1;
     int buf = 0;
 
@@ -128,7 +133,7 @@ __device__ void chain_body(const ChainArgs& a, char* smem)
             for (int e = 0; e < step_e; ++e) {
                 const uint32_t j = (uint32_t)e * nt + tid;
                 if (j >= W) break;
-                const int32_t d = L.D[idx];
+                const int32_t d = L.D[pair_at(j, idx)];
                 bool acc = d <= 0;
                 if (!acc && d <= bound) {
                     const uint64_t tt = t + j;
@@ -155,7 +160,7 @@ __device__ void chain_body(const ChainArgs& a, char* smem)
             for (int e = 0; e < step_e; ++e) {
                 const uint32_t j = (uint32_t)e * nt + tid;
                 if (j > limit) break;
-                const int32_t d = L.D[idx];
+                const int32_t d = L.D[pair_at(j, idx)];
                 if (d > 0 && d <= bound) {
                     const uint64_t tt = t + j;
                     double z;
@@ -180,7 +185,7 @@ __device__ void chain_body(const ChainArgs& a, char* smem)
         // ---------------------------------------------------------- accept
         step_e = 1;
         const uint64_t tstar = t + jstar;
-        const uint32_t istar = (uint32_t)(((uint64_t)idx0 + jstar) % m);
+        const uint32_t istar = pair_at(jstar, (uint32_t)(((uint64_t)idx0 + jstar) % m));
         int u, v;
         pair_of(n, istar, u, v);
         const int32_t dstar = L.D[istar];

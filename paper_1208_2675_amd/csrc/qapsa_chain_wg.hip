@@ -613,6 +613,11 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
     const uint64_t seed = a.seed;
     const uint32_t chain_id = a.chain_id;
     const bool t0_inf = __builtin_isinf(T0);
+    // random proposal order: the ring's second half holds the drawn pairs
+    // ((r << 16) | s) of the iterations whose thresholds the first half holds
+    const bool rnd = (uni(a.flags) & QAP_FLAG_RANDOM_ORDER) != 0;
+    const uint32_t ring_len = rnd ? kRing / 2 : kRing;
+    uint32_t* const ring_pairs = (uint32_t*)L.tau + kRing / 2;
 
     const uint32_t nt_mod = (uint32_t)kThreads % m;
     uint64_t t = uni64(st0.t);
@@ -706,9 +711,14 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         __syncthreads();
         bool ex = false;
         const uint64_t iters = a.iters;
-        for (int i = tid; i < kRing; i += kThreads) {
+        for (int i = tid; i < (int)ring_len; i += kThreads) {
             const uint64_t tt = tau_base + i;
             L.tau[i] = tt < iters ? threshold_at(temps, T0, seed, chain_id, tt, &ex) : 0;
+            if (rnd) {
+                int r = 0, s = 1;
+                if (tt < iters) pair_of_u(n, random_pair_index(seed, chain_id, tt, m), r, s);
+                ring_pairs[i] = ((uint32_t)r << 16) | (uint32_t)s;
+            }
         }
         if (ex) s_flag = 1;
         __syncthreads();
@@ -722,9 +732,17 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         constexpr int KW = decltype(kw_tag)::value;
         constexpr int K = kWaves * KW;
         const uint32_t rem = (uint32_t)min<uint64_t>((uint64_t)K, t_end - t);
-        if (tau_base == ~0ull || t + K > tau_base + kRing) refill();
+        if (tau_base == ~0ull || t + K > tau_base + ring_len) refill();
         int pr[KW], pc[KW];
-        {
+        if (rnd) {
+            const uint32_t* const pk = ring_pairs + (uint32_t)(t - tau_base) + wave * KW;
+#pragma unroll
+            for (int i = 0; i < KW; ++i) {
+                const uint32_t x = uni(pk[i]);
+                pr[i] = (int)(x >> 16);
+                pc[i] = (int)(x & 0xffffu);
+            }
+        } else {
             int r = r0, s = s0;
             advance_by(n, r, s, wave * KW);
 #pragma unroll
@@ -788,7 +806,13 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
             win_iters += rem;
         } else {
             int u = r0, v = s0;
-            advance_by(n, u, v, jstar);
+            if (rnd) {
+                const uint32_t x = uni(ring_pairs[(uint32_t)(t - tau_base) + (uint32_t)jstar]);
+                u = (int)(x >> 16);
+                v = (int)(x & 0xffffu);
+            } else {
+                advance_by(n, u, v, jstar);
+            }
             u = uni(u);
             v = uni(v);
             accept_common(t + jstar, u, v, (int)(uint32_t)key);
@@ -822,7 +846,8 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     jv[k] = (uint32_t)(e + k) * kThreads + tid;
-                    dv[k] = (e + k < step_e && jv[k] < W) ? L.D[idx] : INT_MAX;
+                    const uint32_t ix = rnd ? random_pair_index(seed, chain_id, t + jv[k], m) : idx;
+                    dv[k] = (e + k < step_e && jv[k] < W) ? L.D[ix] : INT_MAX;
                     idx += nt_mod;
                     if (idx >= m) idx -= m;
                 }
@@ -856,7 +881,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
             for (int e = 0; e < step_e; ++e) {
                 const uint32_t j = (uint32_t)e * kThreads + tid;
                 if (j > limit) break;
-                const int32_t d = L.D[idx];
+                const int32_t d = L.D[rnd ? random_pair_index(seed, chain_id, t + j, m) : idx];
                 if (d > 0 && d <= bound) {
                     double z;
                     exact_test(d, temps, T0, seed, chain_id, t + j, &z);
@@ -877,6 +902,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         step_e = 1;
         uint32_t istar = idx0 + (jstar % m);
         if (istar >= m) istar -= m;
+        if (rnd) istar = random_pair_index(seed, chain_id, t + jstar, m);
         istar = uni(istar);
         int u, v;
         pair_of_u(n, istar, u, v);

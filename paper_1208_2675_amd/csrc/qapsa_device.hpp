@@ -46,6 +46,16 @@ __device__ __forceinline__ double uniform_r(uint64_t seed, uint32_t chain, uint6
     return (double)(2ull * u + 1ull) * 0x1p-53;
 }
 
+// Random proposal order: iteration t proposes pair number floor(x2 M / 2^32)
+// of the row-major enumeration (M = n(n-1)/2 pairs), x2 being the third output
+// word of the same generator call that gives r_t.
+__device__ __forceinline__ uint32_t random_pair_index(uint64_t seed, uint32_t chain, uint64_t t, uint32_t m)
+{
+    const uint4 x = philox10(make_uint4((uint32_t)t, (uint32_t)(t >> 32), chain, 0u),
+                             (uint32_t)seed, (uint32_t)(seed >> 32));
+    return __umulhi(x.z, m);
+}
+
 // ---------------------------------------------------------------- cooling
 // temps = [L(1024) | M(1024) | H(...)], T_t = ((T0 * H) * M) * L.
 __device__ __forceinline__ double temperature(const double* __restrict__ temps, double T0, uint64_t t)

@@ -84,6 +84,8 @@ struct DistArgs {
     int32_t quads;
     int32_t a_min, b_min;
     uint32_t kmin, kmax;         // scan window bounds (proposals)
+    uint32_t random_order;       // 1: pairs drawn per iteration (QAP_FLAG_RANDOM_ORDER)
+    uint32_t pad;
     uint64_t spin_limit;         // barrier polls before giving up
     const int32_t* A;
     const int32_t* B;

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libqapsa.so")
 QAP_OK, QAP_E_INVAL, QAP_E_NOT_PERM, QAP_E_RANGE = 0, -1, -2, -3
 QAP_E_NOMEM, QAP_E_DEVICE, QAP_E_UNSUPPORTED, QAP_E_STATE, QAP_E_TIMEOUT = -4, -5, -6, -7, -8
 QAP_MODE_SCRATCH, QAP_MODE_DELTA, QAP_MODE_SCRATCH_STALE = 0, 1, 2
-QAP_FLAG_DELTA_ONLY, QAP_FLAG_SCRATCH_ONLY, QAP_FLAG_MULTI_WG = 1, 2, 4
+QAP_FLAG_DELTA_ONLY, QAP_FLAG_SCRATCH_ONLY, QAP_FLAG_MULTI_WG, QAP_FLAG_RANDOM_ORDER = 1, 2, 4, 8
 
 
 class QapError(RuntimeError):

@@ -84,7 +84,7 @@ def test_host_side_argument_errors(qlib):
                 Q.Schedule(100, 100, float("nan"), 0.99, 1, 0, 0, 0, 0),
                 Q.Schedule(100, 100, 1.0, 1.5, 1, 0, 0, 0, 0), Q.Schedule(0, 0, 1.0, 0.5, 1, 0, 0, 0, 0),
                 Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 7, 0, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 3, 0, 0),
-                Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 8, 0, 0),
+                Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 16, 0, 0),
                 Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 0, 1001, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 0, 0, 1)):
         assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, fake, bad, info, bufs, 0) == Q.QAP_E_INVAL
     assert Q.qap_sa_run(8, fake, fake, None, fake, fake, fake, ok, info, bufs, 0) == Q.QAP_E_INVAL
