@@ -2,7 +2,7 @@
 of the HIP path on one MI355X, single chain vs batched chains, with the CPU
 oracle timed beside it.
 
-    python bench.py [--steps K] [--warmup W] [--sections single,batched,update,serve]
+    python bench.py [--steps K] [--warmup W] [--sections single,batched,update,serve,random]
 
 Headline (``value``): one step is one whole annealing run of the single-chain
 workload -- set-up of B', Delta, cost and schedule, then all I iterations -- on
@@ -20,6 +20,9 @@ Further sections, reported in the same JSON line:
            update: 4N(N-1) for Delta read + write, 8N^2 for A and B' read once).
   serve    a prefix of the served trace (Poisson 200 req/s, N log-uniform in
            [32, 512], I = 1e7): p50/p99 latency and aggregate iterations/s.
+  random   the single-chain workload with the pairs proposed at random instead
+           of in row-major order: iterations/s, parity against the oracle's
+           stored full run, and the oracle timed on a prefix of the same run.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -70,18 +73,42 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(ch, iters_sample: int) -> dict:
+def cpu_baseline(ch, iters_sample: int, order: int = 0) -> dict:
     import oracle
     oracle.build()
     s = oracle.schedule(ch.A, ch.B, ch.p0, ch.iters)
     t0 = time.perf_counter()
     r = oracle.sa_run(ch.A, ch.B, ch.p0, ch.iters, s["T0"], s["alpha"], ch.philox_seed, ch.chain_id,
-                      t_end=iters_sample)
+                      t_end=iters_sample, order=order)
     dt = time.perf_counter() - t0
     return {"value": iters_sample / dt, "unit": "iterations/s", "cores": 1, "kind": "oracle",
             "sample": f"first {iters_sample:.0e} iterations of the same schedule, single thread "
                       f"({r['accepts']} accepts, {dt:.1f} s); the oracle computes every proposal's swap cost "
                       f"from scratch, so its cost per iteration does not depend on the acceptance rate"}
+
+
+def section_random(Q, W, torch, args):
+    """The single-chain workload with random proposal order: one timed run."""
+    ch = W.single_chain(args.workload)
+    log(f"random: workload={args.workload} n={ch.n} iters={ch.iters}")
+    c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id, flags=Q.QAP_FLAG_RANDOM_ORDER).init()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.run()
+    st = c.state()
+    wall = time.perf_counter() - t0
+    parity = None
+    gold_path = os.path.join(ROOT, "tests", "golden", "oracle_runs.json")
+    g = json.load(open(gold_path)).get(f"{args.workload}@{ch.iters}:random") if os.path.exists(gold_path) else None
+    if g:
+        parity = all(int(getattr(st, k)) == g[k] for k in ("accepts", "hash", "cost", "best_cost")) and \
+            c.p.cpu().numpy().tolist() == g["p"]
+    out = {"value": ch.iters / wall, "unit": "iterations/s", "wall_s": wall, "accepts": int(st.accepts),
+           "delta_updates_per_s": int(st.accepts) / wall, "final_cost": int(st.cost),
+           "parity_vs_oracle": parity, "timed": "one run of all I iterations on resident inputs (set-up excluded)"}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ch, min(args.cpu_sample // 3, ch.iters), order=1)
+    return out
 
 
 def section_single(Q, W, torch, args):
@@ -229,7 +256,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n150_asym")
-    ap.add_argument("--sections", default="single,batched,update,serve")
+    ap.add_argument("--sections", default="single,batched,update,serve,random")
     ap.add_argument("--cpu-sample", type=int, default=30_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-iters", type=int, default=10**7)
@@ -263,6 +290,8 @@ def main():
             line["copy_calibration"] = calibrate_copy(torch)
         if "batched" in sections:
             line["batched"] = section_batched(Q, W, torch, args)
+        if "random" in sections:
+            line["random_order"] = section_random(Q, W, torch, args)
         print(json.dumps(line))
         return
     s = section_single(Q, W, torch, args)
@@ -307,6 +336,8 @@ def main():
                             "avg_launch_ms": u["avg_launch_ms"]}
     if "serve" in sections:
         line["serve"] = section_serve(Q, W, torch, args)
+    if "random" in sections:
+        line["random_order"] = section_random(Q, W, torch, args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ch, min(args.cpu_sample, ch.iters))
     print(json.dumps(line))

@@ -134,3 +134,54 @@ def test_batch_matches_oracle_per_chain(orc, Q):
         for k in ("t", "accepts", "hash", "cost", "best_cost", "best_iter", "near_ties"):
             assert st[k] == ref[k], (i, ch.name, k, st[k], ref[k])
         assert np.array_equal(b.perm(i), ref["p"]), (i, ch.name)
+
+
+# ------------------------------------------------------- full-size workloads
+
+def _golden(key):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_runs.json")) as f:
+        return json.load(f)[key]
+
+
+def _check_state(r, g):
+    for k in ("accepts", "hash", "cost", "best_cost", "best_iter", "near_ties"):
+        assert r[k] == g[k], (k, r[k], g[k])
+    assert r["t"] == g["t_end"]
+    assert r["p"].tolist() == g["p"]
+
+
+def _sampled_delta(orc, ch, r, k, seed):
+    rng = np.random.default_rng(seed)
+    n = ch.n
+    for _ in range(k):
+        a_, b_ = sorted(rng.choice(n, 2, replace=False))
+        idx = a_ * (2 * n - a_ - 1) // 2 + b_ - a_ - 1
+        assert r["delta"][idx] == orc.swap_cost(ch.A, ch.B, r["p"], int(a_), int(b_))
+
+
+@pytest.mark.slow
+def test_n150_full_schedule_against_stored_oracle_run(orc, Q):
+    """N = 150 asymmetric, I = 1e8, random order, against the oracle's full run."""
+    g = _golden("n150_asym@100000000:random")
+    ch = W.single_chain("n150_asym")
+    c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id, flags=Q.QAP_FLAG_RANDOM_ORDER).init()
+    assert c.sched.T0 == g["T0"] and c.sched.alpha == g["alpha"]
+    c.run()
+    r = c.result(with_delta=True)
+    _check_state(r, g)
+    _sampled_delta(orc, ch, r, 200, 2)
+
+
+def test_n2000_prefix_against_stored_oracle_run(orc, Q):
+    """N = 2000 symmetric on the multi-workgroup kernel, random order, first 3e5
+    iterations of the I = 1e9 schedule."""
+    g = _golden("n2000_sym@300000:random")
+    ch = W.single_chain("n2000_sym")
+    c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id, flags=Q.QAP_FLAG_RANDOM_ORDER).init()
+    assert c.sched.T0 == g["T0"] and c.sched.alpha == g["alpha"]
+    c.run(300_000)
+    r = c.result(with_delta=True)
+    _check_state(r, g)
+    _sampled_delta(orc, ch, r, 300, 3)
