@@ -93,6 +93,9 @@ def lib():
         L.orc_sa_run_order.restype = C.c_int
         L.orc_random_pair_index.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64]
         L.orc_random_pair_index.restype = C.c_uint64
+        L.orc_tabu_run.argtypes = [C.c_int32, i32p, i32p, i32p, C.POINTER(State), C.c_uint64, C.c_int64,
+                                   i64p, C.c_void_p, C.c_uint64]
+        L.orc_tabu_run.restype = C.c_int
         L.orc_brute_force.argtypes = [C.c_int32, i32p, i32p, i32p, C.POINTER(C.c_uint64)]
         L.orc_brute_force.restype = C.c_int64
         _lib = L
@@ -217,6 +220,28 @@ def sa_run(A, B, p0, iters: int, T0: float, alpha: float, seed: int, chain: int 
     return {"p": p, "state": state, **state.as_dict(),
             "accept_log": acc[:nacc] if acc_cap else None,
             "near_tie_t": tie_t[:nt].copy(), "near_tie_z": tie_z[:nt].copy()}
+
+
+def tabu_run(A, B, p0, t_end: int, tenure: int, state: State | None = None, tabu=None,
+             acc_cap: int = 0) -> dict:
+    """Tabu search over iterations [state.t, t_end) (rules in qap_oracle.c).
+    ``tabu`` (n*n int64) carries the tabu table between calls."""
+    A, B = _mats(A, B)
+    n = A.shape[0]
+    p = np.ascontiguousarray(p0, dtype=np.int32).copy()
+    L = lib()
+    if state is None:
+        state = State()
+        L.orc_state_init(n, A, B, p, C.byref(state))
+    tabu = np.zeros(n * n, dtype=np.int64) if tabu is None else np.ascontiguousarray(tabu, dtype=np.int64).copy()
+    acc = np.zeros((max(acc_cap, 1), 4), dtype=np.int64)
+    rc = L.orc_tabu_run(n, A, B, p, C.byref(state), int(t_end), int(tenure), tabu,
+                        acc.ctypes.data if acc_cap else None, acc_cap)
+    if rc != 0:
+        raise ValueError(f"orc_tabu_run failed with status {rc}")
+    nacc = min(state.accepts, acc_cap)
+    return {"p": p, "state": state, "tabu": tabu, **state.as_dict(),
+            "accept_log": acc[:nacc] if acc_cap else None}
 
 
 def brute_force(A, B) -> tuple[int, np.ndarray, int]:

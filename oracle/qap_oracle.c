@@ -40,6 +40,11 @@
  *                                (Sec. 2.1 lets the next swap be chosen randomly
  *                                or sequentially): iteration t proposes a pair
  *                                drawn from its own counter (reading below).
+ *   orc_tabu_run                 tabu search over the same swap costs, the heuristic
+ *                                whose Delta bookkeeping (Taillard) the method takes
+ *                                over (Sec. 2.2, Sec. 2.4): every iteration evaluates
+ *                                all swaps and makes the best admissible one
+ *                                (reading below).
  *   orc_brute_force              the exact optimum over all N! permutations (N <= 10).
  *
  * Readings where the paper is silent (each is also listed in the design notes):
@@ -57,6 +62,14 @@
  *     row-major enumeration (M = n(n-1)/2), x2 being the third output word of
  *     the same generator call that gives r_t.  Each of the M pairs takes
  *     floor(2^32 / M) or that plus one of the 2^32 values of x2.
+ *   - Tabu search (the paper names it, after Taillard, but fixes no rules):
+ *     when facility i leaves location l at iteration t, assigning i to l is
+ *     tabu for the iterations t' < t + tenure.  The swap (r, s) is tabu at t
+ *     when both of its new assignments, r to p(s) and s to p(r), are; a tabu
+ *     swap is still admissible when it gives a cost below the best seen.
+ *     Iteration t makes the admissible swap of least cost change, the lowest
+ *     row-major pair number among equals; if none is admissible, the swap of
+ *     least cost change among all.  Every iteration makes one swap.
  *   - T_t = ((T0 * H[t >> 20]) * M[(t >> 10) & 1023]) * L[t & 1023] with
  *     L[j] = L[j-1] alpha, M[j] = M[j-1] (L[1023] alpha),
  *     H[j] = H[j-1] (M[1023] L[1023] alpha), all three starting at 1.
@@ -415,6 +428,58 @@ int orc_sa_run(int32_t n, const int32_t *A, const int32_t *B, int32_t *p, orc_st
 {
     return orc_sa_run_order(n, A, B, p, st, iters, t_end, T0, alpha, seed, chain, 0,
                             acc_log, acc_cap, tie_t, tie_z, tie_cap);
+}
+
+/* ------------------------------------------------------------- tabu search */
+
+/*
+ * Iterations st->t .. t_end-1 of a tabu search (rules in the header).  tabu:
+ * n*n int64, tabu[i*n + l] = the first iteration at which facility i may again
+ * be assigned to location l (all zero before the first iteration).  Every
+ * swap cost is computed from scratch (orc_swap_cost) at every iteration.
+ * acc_log (optional): 4 int64 per swap (t, r, s, delta), as for orc_sa_run.
+ */
+int orc_tabu_run(int32_t n, const int32_t *A, const int32_t *B, int32_t *p, orc_state *st,
+                 uint64_t t_end, int64_t tenure, int64_t *tabu, int64_t *acc_log, uint64_t acc_cap)
+{
+    if (n < 2 || st->t > t_end || tenure < 0 || !tabu) return ORC_E_INVAL;
+    if (!orc_is_perm(n, p)) return ORC_E_NOT_PERM;
+    if (orc_check_bounds(n, A, B) != ORC_OK) return ORC_E_RANGE;
+    for (uint64_t t = st->t; t < t_end; ++t) {
+        int found = 0, found_any = 0;
+        int32_t br = 0, bs = 1, ar = 0, as = 1;
+        int64_t bd = 0, ad = 0;
+        for (int32_t r = 0; r < n - 1; ++r) {
+            for (int32_t s = r + 1; s < n; ++s) {
+                const int64_t d = orc_swap_cost(n, A, B, p, r, s);
+                if (!found_any || d < ad) { found_any = 1; ad = d; ar = r; as = s; }
+                const int is_tabu = tabu[(int64_t)r * n + p[s]] > (int64_t)t &&
+                                    tabu[(int64_t)s * n + p[r]] > (int64_t)t;
+                const int admissible = !is_tabu || st->cost + d < st->best_cost;
+                if (admissible && (!found || d < bd)) { found = 1; bd = d; br = r; bs = s; }
+            }
+        }
+        if (!found) { bd = ad; br = ar; bs = as; }
+        /* the facilities leave their locations: returning is tabu for `tenure` iterations */
+        tabu[(int64_t)br * n + p[br]] = (int64_t)t + tenure;
+        tabu[(int64_t)bs * n + p[bs]] = (int64_t)t + tenure;
+        const int32_t tmp = p[br];
+        p[br] = p[bs];
+        p[bs] = tmp;
+        st->cost += bd;
+        if (acc_log && st->accepts < acc_cap) {
+            int64_t *e = acc_log + 4 * st->accepts;
+            e[0] = (int64_t)t; e[1] = br; e[2] = bs; e[3] = bd;
+        }
+        st->accepts++;
+        st->hash += orc_accept_fingerprint(t, br, bs, bd);
+        if (st->cost < st->best_cost) {
+            st->best_cost = st->cost;
+            st->best_iter = t + 1;
+        }
+    }
+    st->t = t_end;
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------ brute force */
