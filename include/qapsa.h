@@ -257,6 +257,43 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
                        const qap_instance_info* info, const qap_run_buffers* bufs,
                        hipStream_t stream);
 
+/* ------------------------------------------------------------- tabu search */
+
+/* Schedule of a tabu search (host struct). */
+typedef struct {
+    uint64_t iters;      /* length of the whole search; iters + tenure < 2^31           */
+    uint64_t t_end;      /* this call runs iterations state.t .. t_end-1; t_end <= iters */
+    int32_t tenure;      /* iterations for which a facility may not return to a location
+                            it left (>= 0)                                              */
+    uint32_t reserved;   /* must be 0                                                   */
+} qap_tabu_schedule;
+
+/*
+ * Tabu search over the same Delta matrix: the heuristic Sec. 2.2 and 2.4 name
+ * as the source of the Delta bookkeeping, which evaluates every swap and makes
+ * one each iteration (Sec. 2.4).  The paper fixes no tabu rules; these are:
+ * when facility i leaves location l at iteration t, returning i to l is tabu
+ * for iterations t' < t + tenure; the swap (r, s) is tabu when both of its new
+ * assignments (r to p(s), s to p(r)) are; a tabu swap is admissible when it
+ * gives a cost below the best seen.  Iteration t makes the admissible swap of
+ * least Delta (lowest packed index among equals), or the least Delta of all
+ * when none is admissible, and updates Delta, B', p and the cost exactly as
+ * qap_sa_run does for an accepted swap.
+ *   A, Bp, p, delta, state, info  as for qap_sa_run (state->accepts counts the
+ *          swaps, one per iteration; a stale Delta is rebuilt first)
+ *   tabu   device, n*n int32, caller-owned: entry i*n + l is the first
+ *          iteration at which facility i may return to location l.  Zero it
+ *          before the first call of a search; keep it between calls.
+ *   bufs   accept_log, phase_cycles and, where qap_single_workgroup says 2,
+ *          workspace (qap_chain_scratch_bytes) are used; temps may be NULL.
+ * One workgroup runs the search: byte-valued instances that
+ * qap_single_workgroup accepts; QAP_E_UNSUPPORTED otherwise.
+ */
+QAP_API int qap_tabu_run(int32_t n, const int32_t* A, int32_t* Bp, int32_t* p, int32_t* delta,
+                         qap_chain_state* state, const qap_tabu_schedule* sched,
+                         const qap_instance_info* info, int32_t* tabu, const qap_run_buffers* bufs,
+                         hipStream_t stream);
+
 /* ----------------------------------------------------------------- batches */
 
 /* One chain of a batched run.  Every pointer is a device pointer; the fields

@@ -215,6 +215,44 @@ QAP_API int qap_single_workgroup(int32_t n, int32_t symmetric, int64_t a_range, 
     return 0;
 }
 
+QAP_API int qap_tabu_run(int32_t n, const int32_t* A, int32_t* Bp, int32_t* p, int32_t* delta,
+                         qap_chain_state* state, const qap_tabu_schedule* sched,
+                         const qap_instance_info* info, int32_t* tabu, const qap_run_buffers* bufs,
+                         hipStream_t stream)
+{
+    if (n < 2 || n > 46340 || !A || !Bp || !p || !delta || !state || !sched || !info || !tabu || !bufs)
+        return QAP_E_INVAL;
+    if (sched->iters == 0 || sched->t_end > sched->iters || sched->tenure < 0 || sched->reserved != 0 ||
+        sched->iters + (uint64_t)sched->tenure >= (1ull << 31))
+        return QAP_E_INVAL;
+    if (info->status != QAP_OK) return info->status;
+    const bool sym = info->symmetric != 0;
+    const bool bytes_ok = (int64_t)info->a_max - info->a_min <= 255 && (int64_t)info->b_max - info->b_min <= 255;
+    const int place = bytes_ok ? wg_place(n, sym) : -1;
+    if (place < 0) return QAP_E_UNSUPPORTED;
+    ChainArgs a{};
+    a.n = n;
+    a.max_step = 16;
+    a.flags = QAP_FLAG_DELTA_ONLY;
+    a.switch_permille = 20;
+    a.a_min = info->a_min;
+    a.b_min = info->b_min;
+    a.A = A; a.Bp = Bp; a.p = p; a.delta = delta; a.state = state;
+    a.temps = bufs->temps;
+    a.acc_log = bufs->accept_log; a.acc_cap = bufs->accept_log ? bufs->accept_cap : 0;
+    a.prof = bufs->phase_cycles;
+    a.iters = sched->iters;
+    a.t_end = sched->t_end;
+    a.T0 = 1.0;
+    a.tabu = tabu;
+    a.tenure = sched->tenure;
+    if (place >= 2) {
+        if (!bufs->workspace || bufs->workspace_bytes < wg_scratch_bytes(n, sym, place)) return QAP_E_INVAL;
+        a.gscratch = bufs->workspace;
+    }
+    return launch_chain_wg(a, sym, place, stream, true);
+}
+
 QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs, const qap_chain_desc* dev_descs,
                              const int32_t* order, const qap_batch_config* cfg, void* workspace,
                              hipStream_t stream)

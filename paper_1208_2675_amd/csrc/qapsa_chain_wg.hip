@@ -529,7 +529,9 @@ struct Chain {
 
 template <int V> struct IC { static constexpr int value = V; };
 
-template <bool SYM, int PL>
+// TABU: tabu search over the same Delta instead of annealing (every iteration
+// takes the best admissible swap; rules at the tabu loop below).
+template <bool SYM, int PL, bool TABU = false>
 __device__ void chain_run(const ChainArgs& a_in, char* smem)
 {
     // The chain's hot scalars live in scalar registers of every wave (all
@@ -542,6 +544,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
     __shared__ int s_flag;
     __shared__ unsigned long long s_prof[QAP_PHASES];
     __shared__ ChainArgs s_arg;
+    __shared__ long long s_asp;   // tabu search: best - cost, the aspiration bound of the next iteration
 
     if (threadIdx.x == 0) s_arg = a_in;
     __syncthreads();
@@ -597,6 +600,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
     }
     const bool delta_current = st0.mode != QAP_MODE_SCRATCH_STALE;
     int mode = (a.flags & kFlagDeltaOnly) ? 1 : (a.flags & kFlagScratchOnly) ? 0 : (st0.mode == QAP_MODE_DELTA);
+    if constexpr (TABU) mode = 1;
     if (mode == 1) {
         if (!delta_current) C.build_delta();
         else if (PL == 0) {   // the caller's Delta is valid for p after qap_delta_init and after every run
@@ -925,6 +929,83 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         bump(QAP_PH_N_DELTA_ACC, 1);
     };
 
+    if constexpr (TABU) {
+        // Tabu search.  When facility i leaves location l at iteration t,
+        // returning i to l is tabu until iteration t + tenure; the swap (r, s)
+        // is tabu when both its new assignments, r to p(s) and s to p(r), are,
+        // and a tabu swap is still admissible when cost + Delta < best cost.
+        // Each iteration makes the admissible swap of least Delta (lowest
+        // packed index among equals), or the least Delta of all when none is
+        // admissible.  Keys (Delta with the sign bit flipped, packed index)
+        // order exactly so, as unsigned 64-bit numbers.
+        int32_t* const T = a.tabu;
+        const int32_t tenure = a.tenure;
+        if (tid == 0) s_asp = best - cost;
+        __syncthreads();
+        const int fq = kThreads / n, cq = kThreads - fq * n;   // one step of the folded walk
+        int f0 = 0, c0 = tid;
+        while (c0 >= n) { c0 -= n; ++f0; }
+        while (t < t_end) {
+            const long long asp = s_asp;
+            const int32_t tt = (int32_t)t;
+            unsigned long long k_adm = ~0ull, k_all = ~0ull;
+            int f = f0, c = c0;
+            for (uint32_t k = tid; k < m; k += kThreads) {
+                const bool first = c < n - 1 - f;
+                const int r = first ? f : n - 2 - f;
+                const int s = first ? f + 1 + c : c;
+                const uint32_t off = rs32(n, r) + (uint32_t)(s - r - 1);
+                const int32_t d = L.D[off];
+                const unsigned long long key = ((unsigned long long)((uint32_t)d ^ 0x80000000u) << 32) | off;
+                k_all = key < k_all ? key : k_all;
+                const bool tabu = T[r * n + L.ps[s]] > tt && T[s * n + L.ps[r]] > tt;
+                if ((!tabu || (long long)d < asp) && key < k_adm) k_adm = key;
+                f += fq;
+                c += cq;
+                if (c >= n) { c -= n; ++f; }
+            }
+            k_adm = wave_min_u64(k_adm);
+            k_all = wave_min_u64(k_all);
+            if (lane == 0) { s_wkey[0][wave] = k_adm; s_wkey[1][wave] = k_all; }
+            __syncthreads();
+            unsigned long long ka = s_wkey[0][0], kl = s_wkey[1][0];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) {
+                ka = s_wkey[0][w] < ka ? s_wkey[0][w] : ka;
+                kl = s_wkey[1][w] < kl ? s_wkey[1][w] : kl;
+            }
+            const unsigned long long key = uni64(ka != ~0ull ? ka : kl);
+            const uint32_t istar = uni((uint32_t)key);
+            const int dstar = (int)((uint32_t)(key >> 32) ^ 0x80000000u);
+            mark(QAP_PH_DELTA_SCAN);
+            int u, v;
+            pair_of_u(n, istar, u, v);
+            u = uni(u);
+            v = uni(v);
+            if (tid == 0) {   // before the swap moves them: u and v leave their locations
+                T[u * n + L.ps[u]] = tt + tenure;
+                T[v * n + L.ps[v]] = tt + tenure;
+            }
+            accept_common(t, u, v, dstar);
+            __syncthreads();
+            C.stage(u, v);
+            if (nrec == kRec) flush();
+            __syncthreads();
+            C.taillard();
+            C.gemv_part(u, v);
+            __syncthreads();
+            C.finish_rows(u, v, false);
+            if (tid == 0) {
+                L.D[istar] = -dstar;
+                s_asp = best - cost;
+            }
+            __threadfence_block();   // the tabu entries written above, for the next iteration's reads
+            __syncthreads();
+            t = uni64(t + 1);
+            mark(QAP_PH_DELTA_UPDATE);
+            bump(QAP_PH_N_DELTA_ACC, 1);
+        }
+    } else
     while (t < t_end) {
         if (mode == 0) {
             if (kw == 1) scratch_round(IC<1>{});
@@ -989,6 +1070,13 @@ __global__ void __launch_bounds__(kThreads) k_chain_wg(ChainArgs a)
 {
     extern __shared__ __align__(16) char smem[];
     chain_run<SYM, PL>(a, smem);
+}
+
+template <bool SYM, int PL>
+__global__ void __launch_bounds__(kThreads) k_tabu_wg(ChainArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    chain_run<SYM, PL, true>(a, smem);
 }
 
 // Many independent chains in one persistent launch: each workgroup takes the
@@ -1126,7 +1214,7 @@ int launch_chain_batch(const BatchArgs& b, int groups, const int count[4], int t
     return QAP_OK;
 }
 
-int launch_chain_wg(const ChainArgs& a, bool symmetric, int place, hipStream_t stream)
+int launch_chain_wg(const ChainArgs& a, bool symmetric, int place, hipStream_t stream, bool tabu)
 {
     if (place < 0 || place >= kPlacements || (place >= 2 && a.gscratch == nullptr)) return QAP_E_INVAL;
     const size_t bytes = lds_wg_bytes(a.n, symmetric, place);
@@ -1135,7 +1223,12 @@ int launch_chain_wg(const ChainArgs& a, bool symmetric, int place, hipStream_t s
          (const void*)k_chain_wg<false, 3>},
         {(const void*)k_chain_wg<true, 0>, (const void*)k_chain_wg<true, 1>, (const void*)k_chain_wg<true, 2>,
          (const void*)k_chain_wg<true, 3>}};
-    const void* fn = fns[symmetric ? 1 : 0][place];
+    const void* tfns[2][kPlacements] = {
+        {(const void*)k_tabu_wg<false, 0>, (const void*)k_tabu_wg<false, 1>, (const void*)k_tabu_wg<false, 2>,
+         (const void*)k_tabu_wg<false, 3>},
+        {(const void*)k_tabu_wg<true, 0>, (const void*)k_tabu_wg<true, 1>, (const void*)k_tabu_wg<true, 2>,
+         (const void*)k_tabu_wg<true, 3>}};
+    const void* fn = (tabu ? tfns : fns)[symmetric ? 1 : 0][place];
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
         return QAP_E_DEVICE;
     ChainArgs args = a;

@@ -43,6 +43,9 @@ struct ChainArgs {
     uint64_t seed;
     uint32_t chain_id;
     uint32_t tie_cap;
+    int32_t* tabu;        // tabu search: n*n table of the first iteration a facility may return to a location
+    int32_t tenure;       // tabu search: iterations a left location stays tabu
+    int32_t pad;
 };
 
 // LDS footprint (bytes) of the one-workgroup chain kernel.
@@ -143,6 +146,6 @@ int wg_quads(int n);
 int wg_place(int n, bool symmetric);
 size_t lds_wg_bytes(int n, bool symmetric, int place);
 size_t wg_scratch_bytes(int n, bool symmetric, int place);
-int launch_chain_wg(const ChainArgs& a, bool symmetric, int place, hipStream_t stream);
+int launch_chain_wg(const ChainArgs& a, bool symmetric, int place, hipStream_t stream, bool tabu = false);
 
 }  // namespace qapsa

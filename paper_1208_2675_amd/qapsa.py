@@ -53,6 +53,10 @@ class Schedule(C.Structure):
                 ("switch_permille", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+class TabuSchedule(C.Structure):
+    _fields_ = [("iters", C.c_uint64), ("t_end", C.c_uint64), ("tenure", C.c_int32), ("reserved", C.c_uint32)]
+
+
 class RunBuffers(C.Structure):
     _fields_ = [("temps", C.c_void_p), ("ties", C.c_void_p), ("tie_cap", C.c_uint32),
                 ("reserved", C.c_uint32), ("accept_log", C.c_void_p), ("accept_cap", C.c_uint64),
@@ -89,6 +93,9 @@ def _load():
     L.qap_sa_run.argtypes = [i32, vp, vp, vp, vp, vp, vp, C.POINTER(Schedule), C.POINTER(InstanceInfo),
                              C.POINTER(RunBuffers), vp]
     L.qap_sa_run.restype = C.c_int
+    L.qap_tabu_run.argtypes = [i32, vp, vp, vp, vp, vp, C.POINTER(TabuSchedule), C.POINTER(InstanceInfo), vp,
+                               C.POINTER(RunBuffers), vp]
+    L.qap_tabu_run.restype = C.c_int
     return L
 
 
@@ -148,6 +155,12 @@ def qap_sa_run(n, A, B, Bp, p, delta, state, sched: Schedule, info: InstanceInfo
                stream=None) -> int:
     return _lib.qap_sa_run(n, _ptr(A), _ptr(B), _ptr(Bp), _ptr(p), _ptr(delta), _ptr(state), C.byref(sched),
                            C.byref(info), C.byref(bufs), _stream(stream))
+
+
+def qap_tabu_run(n, A, Bp, p, delta, state, sched: TabuSchedule, info: InstanceInfo, tabu, bufs: RunBuffers,
+                 stream=None) -> int:
+    return _lib.qap_tabu_run(n, _ptr(A), _ptr(Bp), _ptr(p), _ptr(delta), _ptr(state), C.byref(sched),
+                             C.byref(info), _ptr(tabu), C.byref(bufs), _stream(stream))
 
 
 # ------------------------------------------------------------- conveniences
@@ -231,6 +244,18 @@ class Chain:
         self.sched.t_end = self.iters if t_end is None else int(t_end)
         _check(qap_sa_run(self.n, self.A, self.B, self.Bp, self.p, self.delta, self.state_d, self.sched,
                           self.info, self.buffers(), self.stream), "qap_sa_run")
+        return self
+
+    def tabu(self, t_end: int | None = None, tenure: int | None = None):
+        """Tabu search instead of annealing: iterations state.t .. t_end-1 of a
+        search of ``iters`` iterations (tenure defaults to n).  The tabu table
+        lives on the device between calls."""
+        if getattr(self, "tabu_table", None) is None:
+            self.tabu_table = self.torch.zeros(self.n * self.n, dtype=self.torch.int32, device=self.p.device)
+            self.tenure = self.n if tenure is None else int(tenure)
+        ts = TabuSchedule(self.iters, self.iters if t_end is None else int(t_end), self.tenure, 0)
+        _check(qap_tabu_run(self.n, self.A, self.Bp, self.p, self.delta, self.state_d, ts, self.info,
+                            self.tabu_table, self.buffers(), self.stream), "qap_tabu_run")
         return self
 
     def state(self) -> ChainState:

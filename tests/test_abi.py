@@ -29,7 +29,8 @@ def qlib():
 def test_header_declares_the_boundary():
     names = set(_declared())
     assert {"qap_strerror", "qap_cost", "qap_delta_init", "qap_temp_table_len", "qap_workspace_bytes",
-            "qap_schedule_tables", "qap_sa_run", "qap_batch_workspace_bytes", "qap_sa_run_batch"} <= names
+            "qap_schedule_tables", "qap_sa_run", "qap_batch_workspace_bytes", "qap_sa_run_batch",
+            "qap_tabu_run"} <= names
 
 
 def test_every_declared_symbol_is_exported(qlib):
@@ -100,6 +101,15 @@ def test_host_side_argument_errors(qlib):
     one = (Q.ChainDesc * 1)()
     assert Q.qap_sa_run_batch(1, one, fake, None, Q.BatchConfig(128, 0, 0, None), fake, 0) == Q.QAP_E_INVAL
     assert Q.qap_sa_run_batch(-1, one, fake, None, Q.BatchConfig(256, 0, 0, None), fake, 0) == Q.QAP_E_INVAL
+    # tabu search: schedule limits, the table, and the byte-valued one-workgroup kernel only
+    ts = Q.TabuSchedule(10, 10, 5, 0)
+    assert Q.qap_tabu_run(8, fake, fake, fake, fake, fake, Q.TabuSchedule(10, 10, -1, 0), info, fake, bufs, 0) == Q.QAP_E_INVAL
+    assert Q.qap_tabu_run(8, fake, fake, fake, fake, fake, Q.TabuSchedule(10, 11, 5, 0), info, fake, bufs, 0) == Q.QAP_E_INVAL
+    assert Q.qap_tabu_run(8, fake, fake, fake, fake, fake, Q.TabuSchedule(2**31 - 5, 9, 5, 0), info, fake, bufs,
+                          0) == Q.QAP_E_INVAL
+    assert Q.qap_tabu_run(8, fake, fake, fake, fake, fake, ts, info, None, bufs, 0) == Q.QAP_E_INVAL
+    assert Q.qap_tabu_run(8, fake, fake, fake, fake, fake, ts, wide, fake, bufs, 0) == Q.QAP_E_UNSUPPORTED
+    assert Q.qap_tabu_run(8, fake, fake, fake, fake, fake, ts, bad_info, fake, bufs, 0) == Q.QAP_E_RANGE
     assert Q.qap_cost(0, fake, fake, fake, fake, 0) == Q.QAP_E_INVAL
     assert Q.qap_delta_init(1, fake, fake, fake, fake, fake, fake, None, 0) == Q.QAP_E_INVAL
     assert Q.qap_schedule_tables(0, 0.5, fake, 0) == Q.QAP_E_INVAL
