@@ -2,7 +2,7 @@
 of the HIP path on one MI355X, single chain vs batched chains, with the CPU
 oracle timed beside it.
 
-    python bench.py [--steps K] [--warmup W] [--sections single,batched,update,serve,random]
+    python bench.py [--steps K] [--warmup W] [--sections single,batched,update,serve,random,tabu]
 
 Headline (``value``): one step is one whole annealing run of the single-chain
 workload -- set-up of B', Delta, cost and schedule, then all I iterations -- on
@@ -23,6 +23,9 @@ Further sections, reported in the same JSON line:
   random   the single-chain workload with the pairs proposed at random instead
            of in row-major order: iterations/s, parity against the oracle's
            stored full run, and the oracle timed on a prefix of the same run.
+  tabu     tabu search on the single-chain instance (tenure N): iterations/s
+           (one swap each), the first iterations checked against the oracle's
+           tabu search, which is timed on them.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -85,6 +88,36 @@ def cpu_baseline(ch, iters_sample: int, order: int = 0) -> dict:
             "sample": f"first {iters_sample:.0e} iterations of the same schedule, single thread "
                       f"({r['accepts']} accepts, {dt:.1f} s); the oracle computes every proposal's swap cost "
                       f"from scratch, so its cost per iteration does not depend on the acceptance rate"}
+
+
+def section_tabu(Q, W, torch, args):
+    """Tabu search on the single-chain instance: a prefix checked against the
+    oracle (and timed there), then the timed search."""
+    ch = W.single_chain(args.workload)
+    iters, check = args.tabu_iters, args.tabu_check
+    log(f"tabu: workload={args.workload} n={ch.n} iters={iters} tenure={ch.n}")
+    c = Q.Chain(ch.A, ch.B, ch.p0, iters, ch.philox_seed, ch.chain_id).init()
+    c.tabu(check, ch.n)
+    st_check = c.state()
+    c2 = Q.Chain(ch.A, ch.B, ch.p0, iters, ch.philox_seed, ch.chain_id).init()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c2.tabu(iters, ch.n)
+    st = c2.state()
+    wall = time.perf_counter() - t0
+    import oracle
+    oracle.build()
+    t1 = time.perf_counter()
+    ref = oracle.tabu_run(ch.A, ch.B, ch.p0, check, ch.n)
+    dt = time.perf_counter() - t1
+    parity = all(int(getattr(st_check, k)) == ref[k] for k in ("accepts", "hash", "cost", "best_cost", "best_iter"))
+    return {"value": iters / wall, "unit": "iterations/s", "iters": iters, "tenure": ch.n, "wall_s": wall,
+            "final_cost": int(st.cost), "best_cost": int(st.best_cost),
+            "parity_vs_oracle": parity, "parity_prefix_iters": check,
+            "timed": "one search of all iterations on resident inputs (set-up excluded)",
+            "cpu_baseline": {"value": check / dt, "unit": "iterations/s", "cores": 1, "kind": "oracle",
+                             "sample": f"first {check} iterations of the same search, single thread ({dt:.1f} s); "
+                                       f"every swap cost recomputed in O(N) per iteration"}}
 
 
 def section_random(Q, W, torch, args):
@@ -256,7 +289,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n150_asym")
-    ap.add_argument("--sections", default="single,batched,update,serve,random")
+    ap.add_argument("--sections", default="single,batched,update,serve,random,tabu")
+    ap.add_argument("--tabu-iters", type=int, default=100_000)
+    ap.add_argument("--tabu-check", type=int, default=1500)
     ap.add_argument("--cpu-sample", type=int, default=30_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-iters", type=int, default=10**7)
@@ -292,6 +327,8 @@ def main():
             line["batched"] = section_batched(Q, W, torch, args)
         if "random" in sections:
             line["random_order"] = section_random(Q, W, torch, args)
+        if "tabu" in sections:
+            line["tabu"] = section_tabu(Q, W, torch, args)
         print(json.dumps(line))
         return
     s = section_single(Q, W, torch, args)
@@ -338,6 +375,8 @@ def main():
         line["serve"] = section_serve(Q, W, torch, args)
     if "random" in sections:
         line["random_order"] = section_random(Q, W, torch, args)
+    if "tabu" in sections:
+        line["tabu"] = section_tabu(Q, W, torch, args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ch, min(args.cpu_sample, ch.iters))
     print(json.dumps(line))
