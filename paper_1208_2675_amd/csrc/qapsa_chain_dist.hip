@@ -433,18 +433,20 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             const int s = w + G * c;
             for (int ib = 0; ib <= n - 1; ib += rows_per_pass) {
                 if (ib > 0) {
-                    const int rb = (r0 + ib) % (n - 1);
-                    const uint32_t jb = (rs32(n, rb) + m - idx0) % m;
+                    const int rb = r0 + ib >= n - 1 ? r0 + ib - (n - 1) : r0 + ib;
+                    uint32_t jb = rs32(n, rb) + m - idx0;
+                    if (jb >= m) jb -= m;
                     if (jb >= W) break;
                 }
                 const int i = ib + i_loc;
                 if (i_loc >= rows_per_pass || i > n - 1) continue;
-                const int r = (r0 + i) % (n - 1);
+                const int r = r0 + i >= n - 1 ? r0 + i - (n - 1) : r0 + i;
                 bool ok = s > r && s < n;
                 if (i == 0) ok = ok && s >= s0;
                 if (i == n - 1) ok = ok && s < s0;
                 if (!ok) continue;
-                const uint32_t j = (rs32(n, r) + (uint32_t)(s - r - 1) + m - idx0) % m;
+                uint32_t j = rs32(n, r) + (uint32_t)(s - r - 1) + m - idx0;
+                if (j >= m) j -= m;
                 if (j >= W) continue;
                 if (s != pu && s != pv) test(j, lD[(s / G) * n + r]);
                 else if (r == pu && s == pv) test(j, -pd);
@@ -455,7 +457,8 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             for (int lr = tid; lr < 2 * Rw; lr += nt) {
                 const int rr = w + G * (lr >> 1), x = (lr & 1) ? pv : pu;
                 if (rr == pu || rr == pv || x <= rr) continue;
-                const uint32_t j = (rs32(n, rr) + (uint32_t)(x - rr - 1) + m - idx0) % m;
+                uint32_t j = rs32(n, rr) + (uint32_t)(x - rr - 1) + m - idx0;
+                if (j >= m) j -= m;
                 if (j < W) test(j, lD[(lr >> 1) * n + x]);
             }
         }
@@ -555,22 +558,30 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         if (lane == 0) { s_selfw[wave][0] = self_u; s_selfw[wave][1] = self_v; }
         __syncthreads();   // staged rows complete; everyone has read p
         if (tid == 0) { lps[u] = (int16_t)pu_new; lps[v] = (int16_t)pv_new; }
-        // own rows of B': rows u, v are replaced, the others swap columns u, v
-        for (int lr = 0; lr < Rw; ++lr) {
+        // own rows of B': rows u, v are replaced (whole rows, all threads), the
+        // others swap columns u, v (thread lr for own row lr, in parallel)
+        for (int which = 0; which < 2; ++which) {
+            const int x = which == 0 ? u : v;
+            if (x % G != w) continue;
+            uint8_t* row = lBb + (x / G) * P;
+            const uint8_t* src = which == 0 ? lTu : lTv;
+            for (int k = tid; k < n; k += nt) row[k] = src[k];
+        }
+        for (int lr = tid; lr < Rw; lr += nt) {
             const int r = w + G * lr;
-            uint8_t* row = lBb + lr * P;
-            if (r == u || r == v) {
-                const uint8_t* src = r == u ? lTu : lTv;
-                for (int k = tid; k < n; k += nt) row[k] = src[k];
-            } else if (tid == lr) {
-                const uint8_t x = row[u]; row[u] = row[v]; row[v] = x;
+            if (r != u && r != v) {
+                uint8_t* row = lBb + lr * P;
+                const uint8_t x = row[u];
+                row[u] = row[v];
+                row[v] = x;
             }
         }
         if (nrec == kRec) flush();
-        __syncthreads();
+        // (no barrier: the pass below reads neither B' nor p, and the touched
+        // rows, which read B', come after the next one)
 
-        // pairs of own rows disjoint from {u, v}: for each of this thread's
-        // columns, the entries of up to eight own rows are loaded before any is
+        // pairs of own rows disjoint from {u, v}: the entries of up to eight
+        // own rows in two of this thread's columns are loaded before any is
         // stored (a store to Delta may not move above a later load of it).
         // Entries in columns u, v and in rows u, v get a meaningless value:
         // the first are rewritten below (after a barrier), the rows are stale
@@ -587,23 +598,32 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                     ar[h] = __builtin_bit_cast(v2i16, labp[r]);
                     br[h] = __builtin_bit_cast(v2i16, lbbp[r]);
                 }
+                // two of this thread's columns at a time
+                constexpr int kCols = 2;
+                for (int i0 = 0; i0 < nk; i0 += kCols) {
+                    v2i16 as[kCols], bs[kCols];
+                    int32_t dv[kCols][kRowBatch];
 #pragma unroll
-                for (int i = 0; i < kMaxPerThread; ++i) {
-                    if (i * nt >= n) break;
-                    const int s = tid + i * nt;
-                    const int sc = s < n ? s : 0;
-                    const v2i16 as = __builtin_bit_cast(v2i16, labp[sc]), bs = __builtin_bit_cast(v2i16, lbbp[sc]);
-                    int32_t dv[kRowBatch];
+                    for (int i = 0; i < kCols; ++i) {
+                        const int s = tid + (i0 + i) * nt;
+                        const int sc = s < n ? s : 0;
+                        as[i] = __builtin_bit_cast(v2i16, labp[sc]);
+                        bs[i] = __builtin_bit_cast(v2i16, lbbp[sc]);
 #pragma unroll
-                    for (int h = 0; h < kRowBatch; ++h) {
-                        const int lr = lr0 + h < Rw ? lr0 + h : Rw - 1;
-                        dv[h] = lD[lr * n + sc];
+                        for (int h = 0; h < kRowBatch; ++h) {
+                            const int lr = lr0 + h < Rw ? lr0 + h : Rw - 1;
+                            dv[i][h] = lD[lr * n + sc];
+                        }
                     }
-                    if (s < n) {
+#pragma unroll
+                    for (int i = 0; i < kCols; ++i) {
+                        const int s = tid + (i0 + i) * nt;
+                        if (s >= n) continue;
 #pragma unroll
                         for (int h = 0; h < kRowBatch; ++h)
                             if (lr0 + h < Rw)
-                                lD[(lr0 + h) * n + s] = __builtin_amdgcn_sdot2(ar[h] - as, bs - br[h], dv[h], false);
+                                lD[(lr0 + h) * n + s] =
+                                    __builtin_amdgcn_sdot2(ar[h] - as[i], bs[i] - br[h], dv[i][h], false);
                     }
                 }
             }
@@ -620,6 +640,11 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 if (r == u || r == v) continue;
                 const uint32_t* ar = (const uint32_t*)(lAb + lr * P);
                 const uint32_t* br = (const uint32_t*)(lBb + lr * P);
+                const uint8_t* A_r = lAb + lr * P;
+                const uint8_t* B_r = lBb + lr * P;
+                const int arr = A_r[r], aru = A_r[u], arv = A_r[v], brr = B_r[r], bru = B_r[u], brv = B_r[v];
+                const int sur = lSu[r], suu = lSu[u], svr = lSv[r], svv = lSv[v];
+                const int tur = lTu[r], tuu = lTu[u], tvr = lTv[r], tvv = lTv[v];
                 uint32_t pu_ = 0, pv_ = 0, self = 0;
                 for (int k = lane; k < q; k += 64) {
                     const uint32_t xa = ar[k], xb = br[k];
@@ -631,10 +656,8 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 }
                 const int Pu = wave_sum((int)pu_), Pv = wave_sum((int)pv_), Sr = wave_sum((int)self);
                 if (lane == 0) {
-                    const uint8_t* A_r = lAb + lr * P;
-                    const uint8_t* B_r = lBb + lr * P;
-                    const int du = finish_sym(Pu - Sr - su, A_r[r], A_r[u], lSu[r], lSu[u], B_r[r], B_r[u], lTu[r], lTu[u]);
-                    const int dv = finish_sym(Pv - Sr - sv, A_r[r], A_r[v], lSv[r], lSv[v], B_r[r], B_r[v], lTv[r], lTv[v]);
+                    const int du = finish_sym(Pu - Sr - su, arr, aru, sur, suu, brr, bru, tur, tuu);
+                    const int dv = finish_sym(Pv - Sr - sv, arr, arv, svr, svv, brr, brv, tvr, tvv);
                     lD[lr * n + u] = du;
                     lD[lr * n + v] = dv;
                     s_pub[2 * lr] = du;
