@@ -62,8 +62,12 @@ def tune(iters: int = 10**7, buckets=BUCKETS, candidates=CANDIDATES, log=None) -
 
 
 def _device_key(iters: int) -> str:
+    """Architecture (e.g. gfx950) and schedule length: the marketing name a
+    device reports can change with the runtime's environment, the ISA cannot."""
     import torch
-    return f"{torch.cuda.get_device_name(0)}|{iters}"
+    props = torch.cuda.get_device_properties(0)
+    arch = getattr(props, "gcnArchName", "") or torch.cuda.get_device_name(0)
+    return f"{arch.split(':')[0]}|{iters}"
 
 
 def load_or_tune(iters: int = 10**7, path: str = CACHE, log=None, retune: bool = False) -> dict:
