@@ -239,6 +239,12 @@ __global__ void k_schedule_tables(uint64_t nh, double alpha, double* temps)
     for (uint64_t j = 1; j < nh; ++j) { x = x * step_h; H[j] = x; }
 }
 
+// The launches below report failure through the thread's last-error slot,
+// which also holds the last non-success code of any earlier runtime call of
+// the process (a query that returned "not ready", say).  Reset it first so
+// that the check after the launches sees only their own errors.
+void clear_error() { (void)hipGetLastError(); }
+
 int grid_for(int64_t work, int block)
 {
     int64_t g = (work + block - 1) / block;
@@ -251,6 +257,7 @@ int grid_for(int64_t work, int block)
 int launch_cost(int n, const int32_t* A, const int32_t* B, const int32_t* p, int64_t* cost,
                 hipStream_t stream)
 {
+    clear_error();
     hipLaunchKernelGGL(k_zero64, dim3(1), dim3(1), 0, stream, cost);
     hipLaunchKernelGGL(k_cost_gather, dim3(grid_for((int64_t)n * n, 256)), dim3(256), 0, stream,
                        n, A, B, p, cost);
@@ -262,6 +269,7 @@ int launch_delta_init(int n, const int32_t* A, const int32_t* B, const int32_t* 
                       hipStream_t stream)
 {
     const int64_t nn = (int64_t)n * n;
+    clear_error();
     hipLaunchKernelGGL(k_info_reset, dim3(1), dim3(1), 0, stream, info);
     hipLaunchKernelGGL(k_scan_inputs, dim3(grid_for(nn, 256)), dim3(256), 0, stream, n, A, B, p, info);
     hipLaunchKernelGGL(k_check_bounds, dim3(1), dim3(1), 0, stream, n, info);
@@ -278,6 +286,7 @@ int launch_delta_init(int n, const int32_t* A, const int32_t* B, const int32_t* 
 int launch_schedule_tables(uint64_t iters, double alpha, double* temps, hipStream_t stream)
 {
     const uint64_t nh = temp_table_len(iters) - 2048;
+    clear_error();
     hipLaunchKernelGGL(k_schedule_tables, dim3(1), dim3(1), 0, stream, nh, alpha, temps);
     return hipGetLastError() == hipSuccess ? QAP_OK : QAP_E_DEVICE;
 }

@@ -76,6 +76,10 @@ TIE_BYTES = C.sizeof(NearTie)
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1208_2675_amd.build`")
+    # torch brings its own HIP runtime.  Loading it first makes this library bind
+    # to that same runtime; loaded the other way round, the process would hold
+    # two runtimes, and torch's streams and memory would be foreign to ours.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, u64, i64 = C.c_void_p, C.c_int32, C.c_uint64, C.c_int64
     L.qap_strerror.argtypes = [C.c_int]
