@@ -304,6 +304,31 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     int tb = 0;                                    // tie buffer of the current window
     bool alive = true;
 
+    // Rows u, v of A and (through p) of B' after the swap (u, v): A[u][.],
+    // A[v][.], B'[u][.] = B[p(v)][p(.)] and B'[v][.] = B[p(u)][p(.)], this
+    // thread's columns, all loads issued before any result is used.
+    const int nk = (n + nt - 1) / nt;   // columns per thread (uniform)
+    auto stage_loads = [&](int u, int v, int* ga, int* gb, int* gc, int* gd) __attribute__((always_inline)) {
+        const int pu_new = uni((int)lps[v]), pv_new = uni((int)lps[u]);
+#pragma unroll
+        for (int i = 0; i < kMaxPerThread; ++i) {
+            if (i >= nk) break;
+            const int k = min(tid + i * nt, n - 1);
+            const int pk = k == u ? pu_new : (k == v ? pv_new : (int)lps[k]);
+            ga[i] = a.A[u * n + k];
+            gb[i] = a.A[v * n + k];
+            gc[i] = a.B[pu_new * n + pk];
+            gd[i] = a.B[pv_new * n + pk];
+        }
+    };
+    // Speculative staging: while the previous window accepted its first
+    // proposal (every proposal accepted, or a high acceptance rate), the rows
+    // of this window's first proposal (r0, s0) are requested during the
+    // exchange, so that their latency overlaps it; they are used only when
+    // that proposal is the one accepted, and requested again otherwise.
+    bool last_j0 = false;
+    int ga[kMaxPerThread], gb[kMaxPerThread], gc[kMaxPerThread], gd[kMaxPerThread];
+
     // Publish this workgroup's first acceptance of the window (the minimum of
     // its waves' keys, or none without a scan) and wait for every workgroup's;
     // returns the grid-wide minimum (kNone if there is no acceptance).
@@ -311,12 +336,13 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     // the slot is written, so a workgroup that has seen every slot of this
     // window also sees them.  Slots alternate by window parity: a workgroup
     // can be at most one window ahead of the slowest.
-    auto exchange = [&](bool with_scan) __attribute__((always_inline)) -> unsigned long long {
+    auto exchange = [&](bool with_scan, bool spec) __attribute__((always_inline)) -> unsigned long long {
         wait_stores();   // the published values of the last update have landed
         __syncthreads();
         epoch += 1;
         const unsigned long long tag = (epoch & 1023ull) << 54;
         unsigned long long* slots = slot_base + (epoch & 1) * kMaxGroups;
+        if (wave != 0 && spec) stage_loads(r0, s0, ga, gb, gc, gd);
         if (wave == 0) {
             unsigned long long wk = ~0ull;
             if (with_scan)
@@ -324,6 +350,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             wk = wave_min_u64(wk);
             const unsigned long long own = wk == ~0ull ? kNone : (wk & kKeyBits);
             if (lane == 0) put64(&slots[w], tag | own);
+            if (spec) stage_loads(r0, s0, ga, gb, gc, gd);
             uint64_t spins = 0;
             bool ok = true;
             unsigned long long best_key;
@@ -468,11 +495,13 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             if (lane == 0) s_wkey[wave] = wk;
         }
         if (tid == 0) mark(QAP_PH_DELTA_SCAN);
-        const unsigned long long key = exchange(true);
+        const bool spec = !rnd && last_j0;
+        const unsigned long long key = exchange(true, spec);
         alive = uni(s_ok) != 0;
         if (!alive) break;
         refresh();   // the published values of the last swap are visible now
         const uint32_t jstar = key == kNone ? UINT_MAX : (uint32_t)(key >> 32);
+        last_j0 = jstar == 0;
         // near ties a sequential run would have met; the other buffer, read
         // by everyone before this window's exchange, is cleared for the next
         const int ntie = min(s_ntie[tb], 8);
@@ -517,22 +546,10 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             s_rec[nrec] = Rec{tstar, ((uint32_t)u << 16) | (uint32_t)v, dstar};
         }
         nrec += 1;
-        // staged rows after the swap: A[u][.], A[v][.] and B'[u][.] = B[p(v)][p(.)],
-        // B'[v][.] = B[p(u)][p(.)] with p the permutation after the swap.  All
-        // global loads are issued before any result is used.
+        // staged rows after the swap (requested during the exchange when the
+        // accepted proposal is the window's first and that was speculated)
         const int pu_new = uni((int)lps[v]), pv_new = uni((int)lps[u]);
-        const int nk = (n + nt - 1) / nt;   // columns per thread (uniform)
-        int ga[kMaxPerThread], gb[kMaxPerThread], gc[kMaxPerThread], gd[kMaxPerThread];
-#pragma unroll
-        for (int i = 0; i < kMaxPerThread; ++i) {
-            if (i >= nk) break;
-            const int k = min(tid + i * nt, n - 1);
-            const int pk = k == u ? pu_new : (k == v ? pv_new : (int)lps[k]);
-            ga[i] = a.A[u * n + k];
-            gb[i] = a.A[v * n + k];
-            gc[i] = a.B[pu_new * n + pk];
-            gd[i] = a.B[pv_new * n + pk];
-        }
+        if (!(spec && jstar == 0)) stage_loads(u, v, ga, gb, gc, gd);
         // staged bytes, packed differences and this thread's share of the self
         // terms <A[x][.], B'[x][.]> of x = u, v
         int self_u = 0, self_v = 0;
@@ -684,7 +701,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
 
     // ------------------------------------------------------------ write back
     if (alive) {   // the last swap's published values
-        exchange(false);
+        exchange(false, false);
         alive = s_ok != 0;
     }
     if (alive) refresh();
