@@ -208,7 +208,7 @@ QAP_API int qap_delta_init(int32_t n, const int32_t* A, const int32_t* B, const 
 
 /* Bytes of device workspace a run of an n-facility instance may need
    (qap_run_buffers.workspace): the larger of the multi-workgroup exchange area
-   (32832 + 16 n) and the one-workgroup scratch for asymmetric chains
+   (49216 + 32 n) and the one-workgroup scratch for asymmetric chains
    (qap_chain_scratch_bytes(n, 0)). */
 QAP_API uint64_t qap_workspace_bytes(int32_t n);
 

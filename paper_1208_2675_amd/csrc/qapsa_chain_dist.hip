@@ -195,6 +195,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     __shared__ unsigned long long s_wkey[16];    // first acceptance per wave of the window
     __shared__ unsigned long long s_key;         // the grid-wide first acceptance
     __shared__ int s_ok;
+    __shared__ int s_rf_bad;                     // a published value did not arrive within the spin bound
     __shared__ int s_selfw[16][2];               // per-wave partial self terms of u, v
     __shared__ int s_pub[2 * kMaxOwnRows];       // this workgroup's published Delta(r, u), Delta(r, v), row-major
     __shared__ int s_ntie[2];                    // near ties of the window, by window parity
@@ -225,7 +226,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     int16_t* const lps = L_.ps;
     DistWs* ws = a.ws;
     // published values, workgroup-major: [2 parities][G workgroups][Rmax own rows][2]
-    int* X = a.X;
+    unsigned long long* X = a.X;
     const int Rmax = (n + G - 1) / G;
 
     const bool prof = a.prof != nullptr && w == 0;
@@ -242,7 +243,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     auto bump = [&](int k, unsigned long long x) __attribute__((always_inline)) { if (prof && tid == 0) atomicAdd(&s_prof[k], x); };
 
     // ---------------------------------------------------------------- load
-    if (tid == 0) { s_ok = 1; s_ntie[0] = 0; s_ntie[1] = 0; }
+    if (tid == 0) { s_ok = 1; s_rf_bad = 0; s_ntie[0] = 0; s_ntie[1] = 0; }
     __syncthreads();
     for (int lr = 0; lr < Rw; ++lr) {
         const int r = w + G * lr;
@@ -299,6 +300,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     unsigned long long epoch = 0;
     int par = 0;
     int pu = -1, pv = -1, pd = 0, ppar = 0;       // stale rows of the last swap, its Delta, its X parity
+    uint32_t ptag = 0;                             // the tag its published values carry
     uint32_t kwin = a.kmin;
     int nrec = 0;
     int tb = 0;                                    // tie buffer of the current window
@@ -329,6 +331,35 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     bool last_j0 = false;
     int ga[kMaxPerThread], gb[kMaxPerThread], gc[kMaxPerThread], gd[kMaxPerThread];
 
+    // Stale own rows take the published Delta(., u), Delta(., v) of the last
+    // swap.  Each published value carries the tag of the update that wrote it,
+    // so a reader needs no ordering with the writer's slot: it reads until the
+    // tag is the expected one.  This runs inside the exchange, on the waves
+    // that do not poll (threads first, first + step, ...), so that its loads
+    // overlap the exchange instead of following it.
+    auto refresh_part = [&](int first, int step) __attribute__((always_inline)) {
+        if (pu < 0) return;
+        for (int which = 0; which < 2; ++which) {
+            const int x = which == 0 ? pu : pv, y = which == 0 ? pv : pu;
+            if (x % G != w) continue;
+            int32_t* row = lD + (x / G) * n;
+            unsigned long long* src = X + ppar * G * Rmax * 2 + which;
+            for (int s = first; s < n; s += step) {
+                if (s == x) { row[s] = 0; continue; }
+                if (s == y) { row[s] = -pd; continue; }
+                unsigned long long* e = src + ((s % G) * Rmax + s / G) * 2;
+                unsigned long long xv = get64(e);
+                uint64_t spins = 0;
+                while ((uint32_t)(xv >> 32) != ptag) {
+                    if (++spins > spin_limit || get(&ws->err)) { s_rf_bad = 1; break; }
+                    __builtin_amdgcn_s_sleep(1);
+                    xv = get64(e);
+                }
+                row[s] = (int32_t)(uint32_t)xv;
+            }
+        }
+    };
+
     // Publish this workgroup's first acceptance of the window (the minimum of
     // its waves' keys, or none without a scan) and wait for every workgroup's;
     // returns the grid-wide minimum (kNone if there is no acceptance).
@@ -342,7 +373,10 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         epoch += 1;
         const unsigned long long tag = (epoch & 1023ull) << 54;
         unsigned long long* slots = slot_base + (epoch & 1) * kMaxGroups;
-        if (wave != 0 && spec) stage_loads(r0, s0, ga, gb, gc, gd);
+        if (wave != 0) {
+            if (spec) stage_loads(r0, s0, ga, gb, gc, gd);
+            refresh_part(tid - 64, nt - 64);
+        }
         if (wave == 0) {
             unsigned long long wk = ~0ull;
             if (with_scan)
@@ -373,7 +407,11 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 s_ok = ok;
                 s_key = best_key;
             }
+            if (nwaves == 1) refresh_part(tid, nt);
         }
+        __syncthreads();
+        pu = pv = -1;   // refreshed
+        if (s_rf_bad && tid == 0) { s_ok = 0; put(&ws->err, 1); }
         __syncthreads();
         return uni64(s_key);
     };
@@ -391,24 +429,6 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             hash += x0 + (x1 << 22) + (x2 << 44);
         }
         nrec = 0;
-    };
-
-    // copy the published Delta(., u), Delta(., v) into stale own rows (after
-    // an exchange; the next scan, which reads these rows, follows a barrier)
-    auto refresh = [&]() __attribute__((always_inline)) {
-        if (pu < 0) return;
-        for (int which = 0; which < 2; ++which) {
-            const int x = which == 0 ? pu : pv, y = which == 0 ? pv : pu;
-            if (x % G != w) continue;
-            int32_t* row = lD + (x / G) * n;
-            const int* src = X + ppar * G * Rmax * 2 + which;
-            for (int s = tid; s < n; s += nt) {
-                if (s == x) row[s] = 0;
-                else if (s == y) row[s] = -pd;
-                else row[s] = get((int*)src + ((s % G) * Rmax + s / G) * 2);
-            }
-        }
-        pu = pv = -1;
     };
 
     while (alive && t < t_end) {
@@ -499,7 +519,6 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         const unsigned long long key = exchange(true, spec);
         alive = uni(s_ok) != 0;
         if (!alive) break;
-        refresh();   // the published values of the last swap are visible now
         const uint32_t jstar = key == kNone ? UINT_MAX : (uint32_t)(key >> 32);
         last_j0 = jstar == 0;
         // near ties a sequential run would have met; the other buffer, read
@@ -686,10 +705,11 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         // stores complete during the next scan
         __syncthreads();
         {
-            int* dst = X + ((par * G + w) * Rmax) * 2;
-            for (int i = tid; i < 2 * Rw; i += nt) put(dst + i, s_pub[i]);
+            unsigned long long* dst = X + ((par * G + w) * Rmax) * 2;
+            const unsigned long long tag = (unsigned long long)(uint32_t)epoch << 32;
+            for (int i = tid; i < 2 * Rw; i += nt) put64(dst + i, tag | (uint32_t)s_pub[i]);
         }
-        pu = u; pv = v; pd = dstar; ppar = par;
+        pu = u; pv = v; pd = dstar; ppar = par; ptag = (uint32_t)epoch;
         par ^= 1;
         t = tstar + 1;
         idx0 = istar + 1 == m ? 0 : istar + 1;
@@ -704,7 +724,6 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         exchange(false, false);
         alive = s_ok != 0;
     }
-    if (alive) refresh();
     __syncthreads();
     if (w == 0 && nrec > 0) flush();
     for (int lr = 0; lr < Rw; ++lr) {
@@ -734,9 +753,13 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     }
 }
 
-__global__ void k_ws_reset(DistWs* ws, unsigned long long* slots)
+// Slots and published values start from tag 0, which no window or update of
+// this launch uses (epochs start at 1), so nothing left by an earlier launch
+// or another chain can be taken for this launch's data.
+__global__ void k_ws_reset(DistWs* ws, unsigned long long* slots, unsigned long long* X, int nx)
 {
     for (int i = threadIdx.x; i < 2 * kMaxGroups; i += blockDim.x) slots[i] = 0;   // window 0 is never used
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) X[i] = 0;
     if (threadIdx.x == 0) {
         ws->err = 0;
         ws->nties = 0;
@@ -762,7 +785,8 @@ int launch_chain_dist(const DistArgs& a0, int G, int threads, hipStream_t stream
         return QAP_E_DEVICE;
     if (G > kMaxGroups || threads > 512 || a.n > kMaxPerThread * threads || (a.n + G - 1) / G > kMaxOwnRows)
         return QAP_E_INVAL;
-    hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, stream, a.ws, a.slots);
+    const int Rmax = (a.n + G - 1) / G;
+    hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, stream, a.ws, a.slots, a.X, 2 * 2 * G * Rmax);
     void* kargs[] = {&a};
     if (hipLaunchCooperativeKernel(fn, dim3(G), dim3(threads), kargs, (unsigned)bytes, stream) != hipSuccess)
         return QAP_E_DEVICE;

@@ -77,10 +77,13 @@ static_assert(sizeof(DistWs) == 64, "workspace header");
 constexpr int kMaxGroups = 1024;
 inline size_t dist_ws_bytes(int n)
 {
-    return sizeof(DistWs) + 2 * kMaxGroups * sizeof(unsigned long long) + 4 * sizeof(int) * ((size_t)n + kMaxGroups);
+    return sizeof(DistWs) + 2 * kMaxGroups * sizeof(unsigned long long) +
+           4 * sizeof(unsigned long long) * ((size_t)n + kMaxGroups);
 }
 inline unsigned long long* dist_slots(void* ws) { return (unsigned long long*)((char*)ws + sizeof(DistWs)); }
-inline int* dist_X(void* ws) { return (int*)(dist_slots(ws) + 2 * kMaxGroups); }
+// published Delta(r, u), Delta(r, v) of every row, two buffers by parity; each
+// entry is (tag << 32) | value, the tag naming the update that wrote it
+inline unsigned long long* dist_X(void* ws) { return dist_slots(ws) + 2 * kMaxGroups; }
 
 struct DistArgs {
     int32_t n;
@@ -109,7 +112,7 @@ struct DistArgs {
     uint32_t tie_cap;
     DistWs* ws;
     unsigned long long* slots;   // [2][kMaxGroups]
-    int* X;
+    unsigned long long* X;
 };
 
 int dist_quads(int n);
