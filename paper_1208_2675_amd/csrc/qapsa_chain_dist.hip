@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 unsigned long long xv = get64(e);
                 uint64_t spins = 0;
                 while ((uint32_t)(xv >> 32) != ptag) {
-                    if (++spins > spin_limit || get(&ws->err)) { s_rf_bad = 1; break; }
+                    if (++spins > spin_limit || ((spins & 63) == 0 && get(&ws->err))) { s_rf_bad = 1; break; }
                     __builtin_amdgcn_s_sleep(1);
                     xv = get64(e);
                 }
@@ -398,7 +398,9 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                     best_key = k < best_key ? k : best_key;
                 }
                 if (__all(all)) break;
-                if (++spins > spin_limit || get(&ws->err)) { ok = false; break; }
+                // another workgroup's failure is checked every 64 polls: a load
+                // of its own on every poll would add a round trip to each
+                if (++spins > spin_limit || ((spins & 63) == 0 && get(&ws->err))) { ok = false; break; }
                 __builtin_amdgcn_s_sleep(1);
             }
             best_key = wave_min_u64(best_key);
