@@ -239,21 +239,25 @@ def calibrate_copy(torch, mib: int = 256):
 
 def section_update(Q, W, torch, args):
     """R equal launches of the multi-workgroup kernel, each making K/R forced
-    accepts (T = +inf) on the N=2000 chain; per-launch durations from HIP
-    events on the stream the kernel runs on."""
+    accepts (T = +inf) on the N=2000 chain, after one untimed launch of the
+    same size; per-launch durations from HIP events on the stream the kernel
+    runs on."""
     ch = W.single_chain("n2000_sym")
     n = ch.n
     launches = args.update_launches
     per = args.update_accepts // launches
     log(f"update: n={n} forced accepts={per * launches} in {launches} launches")
-    c = Q.Chain(ch.A, ch.B, ch.p0, per * launches, ch.philox_seed, ch.chain_id, T0=math.inf)
+    # one untimed launch of the same size first (first-launch set-up of the
+    # cooperative kernel), then the timed ones
+    c = Q.Chain(ch.A, ch.B, ch.p0, per * (launches + 1), ch.philox_seed, ch.chain_id, T0=math.inf)
     c.init()
+    c.run(per)
     torch.cuda.synchronize()
     ms = []
     for i in range(launches):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
-        c.run((i + 1) * per)
+        c.run((i + 2) * per)
         ev1.record()
         torch.cuda.synchronize()
         ms.append(ev0.elapsed_time(ev1))
