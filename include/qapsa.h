@@ -121,7 +121,7 @@ typedef struct {
     uint32_t flags;      /* 0 or QAP_FLAG_* below                                      */
     uint32_t switch_permille; /* a chain in scratch mode moves to Delta mode when fewer
                             than this many proposals per 1000 were accepted over the
-                            last 8192 iterations; 0 selects the default (20)          */
+                            last 8192 iterations; 0 selects the default (10)          */
     uint32_t reserved;   /* must be 0                                                 */
 } qap_schedule;
 

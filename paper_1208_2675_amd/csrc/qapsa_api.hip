@@ -132,7 +132,7 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
     a.n = n;
     a.max_step = 16;
     a.flags = sched->flags;
-    a.switch_permille = sched->switch_permille ? sched->switch_permille : 20;
+    a.switch_permille = sched->switch_permille ? sched->switch_permille : kDefaultSwitchPermille;
     a.a_min = info->a_min;
     a.b_min = info->b_min;
     a.A = A; a.Bp = Bp; a.p = p; a.delta = delta; a.state = state;

@@ -1104,7 +1104,7 @@ __global__ void __launch_bounds__(kThreads) k_chain_batch(BatchArgs b)
         a.quads = wg_quads_of(d.n);
         a.max_step = 16;
         a.flags = d.flags;
-        a.switch_permille = d.switch_permille ? d.switch_permille : 20;
+        a.switch_permille = d.switch_permille ? d.switch_permille : kDefaultSwitchPermille;
         a.a_min = d.a_min;
         a.b_min = d.b_min;
         a.A = d.A; a.Bp = d.Bp; a.p = d.p; a.delta = d.delta; a.state = d.state;

@@ -115,6 +115,12 @@ struct DistArgs {
     unsigned long long* X;
 };
 
+// Scratch-to-Delta switch threshold (per mille of accepted proposals over
+// 8192 iterations) when the caller gives none: the fastest of 1-160 for the
+// N = 150 asymmetric single chain over 1e8 iterations on MI355X (7-10; 20 was
+// 1.3% slower, 160 60% slower).  The threshold never changes a run's result.
+constexpr uint32_t kDefaultSwitchPermille = 10;
+
 int dist_quads(int n);
 size_t lds_dist_bytes(int n, int G);
 int launch_chain_dist(const DistArgs& a, int G, int threads, hipStream_t stream);

@@ -86,7 +86,7 @@ def load_or_tune(iters: int = 10**7, path: str = CACHE, log=None, retune: bool =
     return table
 
 
-def switch_for(table: dict | None, n: int, symmetric: bool, default: int = 20) -> int:
+def switch_for(table: dict | None, n: int, symmetric: bool, default: int = 10) -> int:
     """Threshold for a chain of size n (the nearest bucket's)."""
     if not table:
         return default

@@ -14,7 +14,7 @@ def test_switch_for_picks_the_bucket_then_the_nearest():
     assert tune.switch_for(table, 500, True) == 10      # nearest bucket
     assert tune.switch_for(table, 5, True) == 40
     assert tune.switch_for(table, 90, False) == 80      # the only asymmetric bucket
-    assert tune.switch_for(None, 90, False) == 20       # no table: the library default
+    assert tune.switch_for(None, 90, False) == 10       # no table: the library default
 
 
 def test_representatives_have_the_bucket_shape():
