@@ -13,9 +13,14 @@
 //     {u, v} in O(1) each (Sec. 3 (ii): only rows u, v of A and B' are needed,
 //     the symmetric case) and recomputes Delta(r, u), Delta(r, v) of its rows
 //     in O(N) (Sec. 3 (i)), publishing these 2 values per row;
-//   - the owners of rows u and v are then stale for those rows; they copy the
-//     published values in after the next grid barrier.  Until then the scan
-//     reads a pair (r, s) from row r instead of row s when s is stale.
+//   - the owners of rows u and v are then stale for those rows; they read the
+//     published values (tagged with the update that wrote them) during the
+//     next exchange.  Until then the scan reads a pair (r, s) from row r
+//     instead of row s when s is stale.
+// While windows accept their first proposal, the rows of the next window's
+// first proposal are requested during the exchange (speculative staging).
+// Random proposal order (QAP_FLAG_RANDOM_ORDER): every workgroup draws the
+// whole window and tests the proposals it holds.
 // The scan (Sec. 3 (ii)) tests a window of proposals against the current
 // Delta: proposal (r, s), r < s, is tested by the owner of row s, so one
 // window spreads over all workgroups; each contributes its first acceptance to

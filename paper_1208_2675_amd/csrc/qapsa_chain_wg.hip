@@ -29,7 +29,10 @@
 //                  {u,v} are recomputed in O(N) (Sec. 3 (i)).
 // A chain starts in scratch mode and moves to Delta mode once the acceptance
 // rate over a window of iterations falls under a threshold (or is pinned to one
-// mode by a flag).
+// mode by a flag).  Proposals run in row-major order, or at random with
+// QAP_FLAG_RANDOM_ORDER (drawn pairs kept beside the acceptance thresholds).
+// The same routine with a tabu flag runs tabu search over the same Delta: the
+// best admissible swap per iteration instead of the first accepted one.
 //
 // The swap cost in O(N) uses dot products of byte rows (v_dot4_u32_u8):
 //   sum_k (a_kr - a_ks)(b_ks - b_kr) = <a.r, b.s> + <a.s, b.r> - <a.r, b.r> - <a.s, b.s>
