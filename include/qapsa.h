@@ -247,9 +247,10 @@ QAP_API int qap_schedule_tables(uint64_t iters, double alpha, double* temps, hip
  * QAP_E_STATE on a stale one.  The run is identical whatever the split of
  * [0, iters) into calls and whichever mode is active.
  * Kernels: one workgroup holds the chain when its matrices fit one CU's LDS;
- * otherwise (symmetric instances up to a few thousand facilities) the chain
+ * otherwise (symmetric instances up to about 2600 facilities) the chain
  * is spread over many workgroups of one cooperative launch, which needs
- * bufs->workspace.  Returns QAP_E_UNSUPPORTED when no kernel of this build
+ * bufs->workspace; larger ones that qap_single_workgroup accepts run on one
+ * workgroup with Delta, A and B' in bufs->workspace.  Returns QAP_E_UNSUPPORTED when no kernel of this build
  * handles n and the value ranges, QAP_E_RANGE when info->status says so.
  */
 QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int32_t* p, int32_t* delta,

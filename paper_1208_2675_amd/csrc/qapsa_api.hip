@@ -192,6 +192,14 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
             d.X = dist_X(bufs->workspace);
             return launch_chain_dist(d, G, 512, stream);
         }
+        // beyond the multi-workgroup kernel's LDS budget: one workgroup with
+        // Delta, A and B' in device memory
+        const int wp = wg_place(n, sym);
+        if (wp >= 2) {
+            if (!bufs->workspace || bufs->workspace_bytes < wg_scratch_bytes(n, sym, wp)) return QAP_E_INVAL;
+            a.gscratch = bufs->workspace;
+            return launch_chain_wg(a, sym, wp, stream);
+        }
     }
     // 16-bit kernel (Delta mode only)
     if (!fits16(info->a_min, info->a_max) || !fits16(info->b_min, info->b_max)) return QAP_E_UNSUPPORTED;

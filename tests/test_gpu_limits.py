@@ -1,0 +1,86 @@
+"""The largest instances the kernels take, at their real shapes: the largest
+asymmetric and symmetric chains one workgroup holds (Delta, A and B' in device
+memory), and a symmetric chain of N = 2200 on the multi-workgroup kernel.  Every
+proposal is accepted (T = +inf), so the permutation after k iterations is the
+product of the first k row-major transpositions; the cost must equal Eq. (1)
+and sampled Delta entries their definition, from the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1208_2675_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1208_2675_amd import qapsa
+    return qapsa
+
+
+def _largest_one_workgroup(Q, symmetric, ra, rb):
+    lo, hi = 2, 20000
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if Q.qap_single_workgroup(mid, int(symmetric), ra, rb) != 0:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
+
+
+def _check_forced(orc, Q, A, B, p0, iters, flags, samples=150):
+    n = A.shape[0]
+    print(f"[case] limits n={n} iters={iters} flags={flags}", flush=True)
+    c = Q.Chain(A, B, p0, iters, 3, 0, T0=math.inf, flags=flags).init()
+    c.run()
+    r = c.result(with_delta=True)
+    assert r["status"] == 0 and r["accepts"] == iters
+    p = p0.copy()
+    k = 0
+    for a in range(n):
+        for b in range(a + 1, n):
+            if k == iters:
+                break
+            p[[a, b]] = p[[b, a]]
+            k += 1
+        if k == iters:
+            break
+    assert np.array_equal(r["p"], p)
+    assert r["cost"] == orc.cost(A, B, p)
+    rng = np.random.default_rng(n)
+    for _ in range(samples):
+        a_, b_ = sorted(rng.choice(n, 2, replace=False))
+        idx = a_ * (2 * n - a_ - 1) // 2 + b_ - a_ - 1
+        assert r["delta"][idx] == orc.swap_cost(A, B, p, int(a_), int(b_)), (a_, b_)
+    row = int(rng.integers(n))
+    assert np.array_equal(r["Bp"][row], B[p[row]][p])
+
+
+@pytest.mark.slow
+def test_largest_asymmetric_one_workgroup(orc, Q):
+    A, B = W.asym_sparse_grid(3700, (430, 1))
+    n = _largest_one_workgroup(Q, False, int(A.max() - A.min()), int(B.max() - B.min()))
+    A, B = W.asym_sparse_grid(n, (430, 1))
+    assert Q.qap_single_workgroup(n, 0, int(A.max() - A.min()), int(B.max() - B.min())) == 2
+    _check_forced(orc, Q, A, B, W.random_perm(n, (431, 1)), 60, Q.QAP_FLAG_DELTA_ONLY)
+
+
+@pytest.mark.slow
+def test_largest_symmetric_one_workgroup(orc, Q):
+    """Beyond the multi-workgroup kernel's LDS budget the chain runs on one
+    workgroup with its state in device memory."""
+    A, B = W.sym_uniform(3700, (432, 1))
+    n = _largest_one_workgroup(Q, True, int(A.max() - A.min()), int(B.max() - B.min()))
+    A, B = W.sym_uniform(n, (432, 1))
+    _check_forced(orc, Q, A, B, W.random_perm(n, (433, 1)), 60, Q.QAP_FLAG_DELTA_ONLY)
+
+
+def test_symmetric_multi_workgroup_n2200(orc, Q):
+    A, B = W.sym_uniform(2200, (434, 1))
+    _check_forced(orc, Q, A, B, W.random_perm(2200, (435, 1)), 3000, 0)
