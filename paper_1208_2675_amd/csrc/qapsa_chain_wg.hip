@@ -1185,11 +1185,14 @@ int launch_chain_batch(const BatchArgs& b, int groups, const int count[4], int t
         return QAP_OK;
     }
     // the kinds run side by side: the first on the caller's stream, the others
-    // on side streams forked from it and joined back
+    // on side streams forked from it and joined back.  The placements of the
+    // largest chains are launched first, so that their workgroups (the
+    // longest-running ones) are dispatched before the small chains take the
+    // CUs.
     hipStream_t used[kPlacements];
     hipEvent_t joins[kPlacements];
     int nused = 0;
-    for (int pl = 0; pl < kPlacements; ++pl) {
+    for (int pl = kPlacements - 1; pl >= 0; --pl) {
         if (g[pl] == 0) continue;
         if (nused == 0) {
             used[nused++] = stream;
@@ -1205,7 +1208,7 @@ int launch_chain_batch(const BatchArgs& b, int groups, const int count[4], int t
         ++nused;
     }
     int k = 0;
-    for (int pl = 0; pl < kPlacements; ++pl) {
+    for (int pl = kPlacements - 1; pl >= 0; --pl) {
         if (g[pl] == 0) continue;
         if (hipLaunchKernel(fns[pl], dim3(g[pl]), dim3(kThreads), kargs, lds[pl], used[k]) != hipSuccess)
             return QAP_E_DEVICE;
