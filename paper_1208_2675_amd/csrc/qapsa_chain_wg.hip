@@ -1160,20 +1160,34 @@ int launch_chain_batch(const BatchArgs& b, int groups, const int count[4], int t
     const void* fns[kPlacements] = {(const void*)k_chain_batch<0>, (const void*)k_chain_batch<1>,
                                     (const void*)k_chain_batch<2>, (const void*)k_chain_batch<3>};
     int g[kPlacements] = {0, 0, 0, 0};
+    double full[kPlacements] = {0, 0, 0, 0};   // workgroups of the placement that fill the GPU
     int kinds = 0;
     for (int pl = 0; pl < kPlacements; ++pl) {
         if (count[pl] == 0) continue;
         kinds += 1;
         if (hipFuncSetAttribute(fns[pl], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds[pl]) != hipSuccess)
             return QAP_E_DEVICE;
-        int gg = groups;
-        if (gg <= 0) {
-            int per_cu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fns[pl], kThreads, lds[pl]) != hipSuccess)
-                return QAP_E_DEVICE;
-            gg = (per_cu < 1 ? 1 : per_cu) * cus;
-        }
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fns[pl], kThreads, lds[pl]) != hipSuccess)
+            return QAP_E_DEVICE;
+        full[pl] = (double)(per_cu < 1 ? 1 : per_cu) * cus;
+        const int gg = groups > 0 ? groups : (int)full[pl];
         g[pl] = gg > count[pl] ? count[pl] : gg;
+    }
+    // The kernels run side by side, and the hardware may dispatch them in any
+    // order.  So that none of them waits for another's workgroups to finish,
+    // all of them must be resident at once: when their shares of the GPU add
+    // up to more than one, the placements of the smaller chains get fewer
+    // (persistent) workgroups, each then running more chains in turn.
+    if (groups <= 0 && kinds > 1) {
+        double used = 0;
+        for (int pl = kPlacements - 1; pl >= 0; --pl) {
+            if (g[pl] == 0) continue;
+            const double left = 1.0 - used;
+            const int fit = (int)(left * full[pl]);
+            if (g[pl] > fit) g[pl] = fit < 1 ? 1 : fit;
+            used += g[pl] / full[pl];
+        }
     }
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, stream, b.ws);
     BatchArgs args = b;
