@@ -1101,7 +1101,9 @@ __global__ void __launch_bounds__(kThreads) k_chain_batch(BatchArgs b)
         if (idx >= b.n_chains) break;
         const int c = b.order ? b.order[idx] : idx;
         const qap_chain_desc d = b.descs[c];
-        if (wg_placement(d.n, d.symmetric != 0) != PL) continue;
+        int pc = wg_placement(d.n, d.symmetric != 0);
+        if (pc < b.min_place) pc = b.min_place;
+        if (pc != PL) continue;
         ChainArgs a{};
         a.n = d.n;
         a.quads = wg_quads_of(d.n);

@@ -132,7 +132,7 @@ struct BatchWs {
 };
 struct BatchArgs {
     int32_t n_chains;
-    int32_t pad;
+    int32_t min_place;            // chains of a smaller placement run in this one
     const qap_chain_desc* descs;
     const int32_t* order;
     BatchWs* ws;
