@@ -65,7 +65,10 @@ typedef enum {
     QAP_E_DEVICE = -5,       /* a HIP runtime call failed                              */
     QAP_E_UNSUPPORTED = -6,  /* no kernel in this build handles the request            */
     QAP_E_STATE = -7,        /* a chain state that is not ready (see qap_chain_state)  */
-    QAP_E_TIMEOUT = -8       /* a grid barrier of a multi-workgroup run did not complete */
+    QAP_E_TIMEOUT = -8,      /* a grid barrier of a multi-workgroup run did not complete */
+    QAP_E_TIE_OVERFLOW = -9  /* more near ties of Eq. (2) in one scan window than the
+                                multi-workgroup kernel can record exactly; the run stops
+                                rather than report a near-tie count that is too low    */
 } qap_status;
 
 /* Facts about an instance and start permutation, written by qap_delta_init. */
@@ -138,6 +141,10 @@ typedef struct {
                                      third output word of the generator call that gives r_t.
                                      A different run from the default order; resumed slices
                                      must keep the flag                                       */
+#define QAP_FLAG_SINGLE_WG 16u    /* run on one workgroup wherever one can hold the chain (with
+                                     Delta, A and B' in bufs->workspace where LDS runs out),
+                                     never on the multi-workgroup kernel (qap_sa_run only; the
+                                     result is the same; excludes QAP_FLAG_MULTI_WG)          */
 
 /* Device buffers a run reads or appends to (host struct of device pointers). */
 typedef struct {
@@ -223,6 +230,27 @@ QAP_API uint64_t qap_temp_table_len(uint64_t iters);
  * the paper; this is the geometric one, evaluable for any t in O(1).
  */
 QAP_API int qap_schedule_tables(uint64_t iters, double alpha, double* temps, hipStream_t stream);
+
+/*
+ * The geometric cooling schedule of a run (host only, no device work).  The
+ * paper lowers T after every iteration (Sec. 2.1) without fixing the form;
+ * this library reads it as geometric from T0 to final_ratio * T0 over `iters`
+ * iterations, with T0 the mean |Delta| of the starting Delta matrix (step (a)
+ * of Sec. 2.2):
+ *   T0    = (double) info->sum_abs_delta / (double) (n (n - 1) / 2), one IEEE division
+ *   alpha = pow(final_ratio, 1 / (iters - 1)), or 1 when iters == 1
+ *   n      instance size (>= 2), the one qap_delta_init was called with
+ *   info   host copy of the qap_instance_info qap_delta_init wrote
+ *   iters  I, the length of the whole schedule (>= 1)
+ *   final_ratio  T_{I-1} / T0, in (0, 1]; 1e-3 for the standard workloads
+ *   sched  host, written: iters, t_end (= iters), T0 and alpha; seed, chain_id,
+ *          flags, switch_permille and reserved are left as the caller set them
+ * Returns QAP_E_INVAL for n < 2, iters == 0, a ratio outside (0, 1] or a null
+ * pointer, info->status when it is not QAP_OK, and QAP_E_INVAL when T0 would
+ * be 0 (every swap cost 0: the schedule of Eq. (2) is then undefined).
+ */
+QAP_API int qap_schedule_init(int32_t n, const qap_instance_info* info, uint64_t iters, double final_ratio,
+                              qap_schedule* sched);
 
 /*
  * Steps (b)-(e) of Sec. 2.2 for one chain: iterations state->t .. sched->t_end-1.

@@ -21,9 +21,11 @@ int check_schedule(const qap_schedule* s)
     if (s->iters == 0 || s->t_end > s->iters) return QAP_E_INVAL;
     if (!(s->T0 > 0.0)) return QAP_E_INVAL;                // rejects NaN and <= 0; +inf allowed
     if (!(s->alpha > 0.0) || s->alpha > 1.0) return QAP_E_INVAL;
-    if ((s->flags & ~(QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY | QAP_FLAG_MULTI_WG | QAP_FLAG_RANDOM_ORDER)) != 0)
+    if ((s->flags & ~(QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY | QAP_FLAG_MULTI_WG | QAP_FLAG_RANDOM_ORDER |
+                      QAP_FLAG_SINGLE_WG)) != 0)
         return QAP_E_INVAL;
     if ((s->flags & QAP_FLAG_DELTA_ONLY) && (s->flags & QAP_FLAG_SCRATCH_ONLY)) return QAP_E_INVAL;
+    if ((s->flags & QAP_FLAG_MULTI_WG) && (s->flags & QAP_FLAG_SINGLE_WG)) return QAP_E_INVAL;
     if (s->switch_permille > 1000 || s->reserved != 0) return QAP_E_INVAL;
     return QAP_OK;
 }
@@ -68,6 +70,7 @@ QAP_API const char* qap_strerror(int status)
     case QAP_E_UNSUPPORTED: return "no kernel in this build handles the request";
     case QAP_E_STATE: return "chain state is not ready";
     case QAP_E_TIMEOUT: return "a grid barrier did not complete";
+    case QAP_E_TIE_OVERFLOW: return "too many near ties in one scan window to record exactly";
     default: return "unknown status";
     }
 }
@@ -116,12 +119,31 @@ QAP_API int qap_schedule_tables(uint64_t iters, double alpha, double* temps, hip
     return launch_schedule_tables(iters, alpha, temps, stream);
 }
 
-QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int32_t* p, int32_t* delta,
-                       qap_chain_state* state, const qap_schedule* sched,
-                       const qap_instance_info* info, const qap_run_buffers* bufs, hipStream_t stream)
+QAP_API int qap_schedule_init(int32_t n, const qap_instance_info* info, uint64_t iters, double final_ratio,
+                              qap_schedule* sched)
 {
-    if (n < 2 || n > 46340 || !A || !B || !Bp || !p || !delta || !state || !info || !bufs || !bufs->temps)
-        return QAP_E_INVAL;
+    if (n < 2 || !info || !sched || iters == 0 || !(final_ratio > 0.0) || final_ratio > 1.0) return QAP_E_INVAL;
+    if (info->status != QAP_OK) return info->status;
+    if (info->sum_abs_delta <= 0) return QAP_E_INVAL;
+    const int64_t m = (int64_t)n * (n - 1) / 2;
+    sched->iters = iters;
+    sched->t_end = iters;
+    sched->T0 = (double)info->sum_abs_delta / (double)m;
+    sched->alpha = iters == 1 ? 1.0 : pow(final_ratio, 1.0 / (double)(iters - 1));
+    return QAP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Kernel selection and launch of one chain's run; the workspace comes from
+// bufs.
+// A workspace smaller than the chosen kernel needs is reported as ws_short.
+int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int32_t* p, int32_t* delta,
+                qap_chain_state* state, const qap_schedule* sched, const qap_instance_info* info,
+                const qap_run_buffers* bufs, hipStream_t stream, int ws_short)
+{
     const int rc = check_schedule(sched);
     if (rc != QAP_OK) return rc;
     if (info->status != QAP_OK) return info->status;
@@ -149,18 +171,21 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
     // byte-valued kernel: value ranges of A and B fit 0..255 after shifting
     const bool bytes_ok = (int64_t)info->a_max - info->a_min <= 255 && (int64_t)info->b_max - info->b_min <= 255;
     const bool multi = (sched->flags & QAP_FLAG_MULTI_WG) != 0 && sym;
-    a.flags &= ~QAP_FLAG_MULTI_WG;
+    const bool single = (sched->flags & QAP_FLAG_SINGLE_WG) != 0;
+    a.flags &= ~(QAP_FLAG_MULTI_WG | QAP_FLAG_SINGLE_WG);
     int place = bytes_ok && !multi ? wg_place(n, sym) : -1;
-    if (sym && place == 3) place = -1;   // large symmetric chains: many workgroups share the Delta update
+    // large symmetric chains: many workgroups share the Delta update, unless one is asked for
+    if (sym && place == 3 && !single) place = -1;
     // one workgroup: Delta, then A, then B' in device memory where LDS runs out
     if (place >= 0 && place <= 1) return launch_chain_wg(a, sym, place, stream);
     if (place >= 2) {
-        if (!bufs->workspace || bufs->workspace_bytes < wg_scratch_bytes(n, sym, place)) return QAP_E_INVAL;
+        if (!bufs->workspace) return QAP_E_INVAL;
+        if (bufs->workspace_bytes < wg_scratch_bytes(n, sym, place)) return ws_short;
         a.gscratch = bufs->workspace;
         return launch_chain_wg(a, sym, place, stream);
     }
     // many workgroups, one cooperative launch: symmetric byte-valued instances
-    if (bytes_ok && sym) {
+    if (bytes_ok && sym && !single) {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -170,7 +195,8 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
         if (G < 2) G = 2;
         while (G < cus && lds_dist_bytes(n, G) > budget) ++G;
         if (lds_dist_bytes(n, G) <= budget) {
-            if (!bufs->workspace || bufs->workspace_bytes < dist_ws_bytes(n)) return QAP_E_INVAL;
+            if (!bufs->workspace) return QAP_E_INVAL;
+            if (bufs->workspace_bytes < dist_ws_bytes(n)) return ws_short;
             DistArgs d{};
             d.n = n;
             d.a_min = info->a_min;
@@ -196,7 +222,8 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
         // Delta, A and B' in device memory
         const int wp = wg_place(n, sym);
         if (wp >= 2) {
-            if (!bufs->workspace || bufs->workspace_bytes < wg_scratch_bytes(n, sym, wp)) return QAP_E_INVAL;
+            if (!bufs->workspace) return QAP_E_INVAL;
+            if (bufs->workspace_bytes < wg_scratch_bytes(n, sym, wp)) return ws_short;
             a.gscratch = bufs->workspace;
             return launch_chain_wg(a, sym, wp, stream);
         }
@@ -210,6 +237,19 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
     a.pitch = n | 1;
     const int threads = n >= 64 ? 1024 : 256;
     return launch_chain_lds(a, sym, a_lds, threads, stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int32_t* p, int32_t* delta,
+                       qap_chain_state* state, const qap_schedule* sched,
+                       const qap_instance_info* info, const qap_run_buffers* bufs, hipStream_t stream)
+{
+    if (n < 2 || n > 46340 || !A || !B || !Bp || !p || !delta || !state || !info || !bufs || !bufs->temps)
+        return QAP_E_INVAL;
+    return sa_run_impl(n, A, B, Bp, p, delta, state, sched, info, bufs, stream, QAP_E_INVAL);
 }
 
 QAP_API uint64_t qap_batch_workspace_bytes(void) { return sizeof(BatchWs); }

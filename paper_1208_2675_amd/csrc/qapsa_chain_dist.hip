@@ -95,8 +95,16 @@ __device__ __forceinline__ int finish_sym(int S, int arr, int ars, int asr, int 
 // Wait until this wave's global stores have completed (vmcnt = 0).
 __device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-__device__ __forceinline__ void put(int* p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ __forceinline__ int get(int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Failure codes of a run in DistWs::err; the larger one wins when several
+// workgroups fail at once (every other workgroup stops at its next exchange).
+constexpr int kErrTimeout = 1;
+constexpr int kErrTieOverflow = 2;
+__device__ __forceinline__ void raise_err(int* p, int code)
+{
+    __hip_atomic_fetch_max(p, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 struct Lds {
     int32_t* D;      // [R][n] full rows of Delta
@@ -184,6 +192,7 @@ __device__ __forceinline__ unsigned long long get64(unsigned long long* p)
 }
 
 constexpr int kMaxPerThread = 8;   // n <= 8 * threads
+constexpr int kTieSlots = 16;      // near ties one workgroup records per scan window
 constexpr int kMaxOwnRows = 64;    // rows per workgroup (n <= 64 G)
 
 // Eq. (2) for Delta > 0 at iteration t, out of line (keeps the FP64 log and the
@@ -204,9 +213,9 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     __shared__ int s_selfw[16][2];               // per-wave partial self terms of u, v
     __shared__ int s_pub[2 * kMaxOwnRows];       // this workgroup's published Delta(r, u), Delta(r, v), row-major
     __shared__ int s_ntie[2];                    // near ties of the window, by window parity
-    __shared__ unsigned long long s_tie_j[2][8];
-    __shared__ int s_tie_d[2][8];
-    __shared__ double s_tie_z[2][8];
+    __shared__ unsigned long long s_tie_j[2][kTieSlots];
+    __shared__ int s_tie_d[2][kTieSlots];
+    __shared__ double s_tie_z[2][kTieSlots];
     __shared__ Rec s_rec[kRec];
     __shared__ unsigned long long s_prof[QAP_PHASES];
 
@@ -310,6 +319,8 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     int nrec = 0;
     int tb = 0;                                    // tie buffer of the current window
     bool alive = true;
+    bool bound_ready = false;                      // bound_next holds the rejection bound of the next window
+    int32_t bound_next = 0;
 
     // Rows u, v of A and (through p) of B' after the swap (u, v): A[u][.],
     // A[v][.], B'[u][.] = B[p(v)][p(.)] and B'[v][.] = B[p(u)][p(.)], this
@@ -410,7 +421,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             }
             best_key = wave_min_u64(best_key);
             if (lane == 0) {
-                if (!ok) put(&ws->err, 1);
+                if (!ok) raise_err(&ws->err, kErrTimeout);
                 s_ok = ok;
                 s_key = best_key;
             }
@@ -418,7 +429,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         }
         __syncthreads();
         pu = pv = -1;   // refreshed
-        if (s_rf_bad && tid == 0) { s_ok = 0; put(&ws->err, 1); }
+        if (s_rf_bad && tid == 0) { s_ok = 0; raise_err(&ws->err, kErrTimeout); }
         __syncthreads();
         return uni64(s_key);
     };
@@ -441,7 +452,9 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     while (alive && t < t_end) {
         // ------------------------------------------------------------ scan
         const uint32_t W = (uint32_t)min<uint64_t>(min<uint64_t>((uint64_t)kwin, t_end - t), (uint64_t)m);
-        const int32_t bound = reject_bound(temperature(temps, T0, t));
+        // after an accepted swap the bound of this window was loaded during the update
+        const int32_t bound = bound_ready ? bound_next : reject_bound(temperature(temps, T0, t));
+        bound_ready = false;
         unsigned long long mine = ~0ull;
         auto test = [&](uint32_t j, int d) __attribute__((always_inline)) {
             bool acc = d <= 0;
@@ -452,7 +465,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 acc = exact_test(d, temps, T0, seed, chain_id, t + j, &z);
                 if (fabs(z) < kNearTie) {
                     const int slot = atomicAdd(&s_ntie[tb], 1);
-                    if (slot < 8) { s_tie_j[tb][slot] = j; s_tie_d[tb][slot] = d; s_tie_z[tb][slot] = z; }
+                    if (slot < kTieSlots) { s_tie_j[tb][slot] = j; s_tie_d[tb][slot] = d; s_tie_z[tb][slot] = z; }
                 }
             }
             if (acc) {
@@ -529,9 +542,17 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         const uint32_t jstar = key == kNone ? UINT_MAX : (uint32_t)(key >> 32);
         last_j0 = jstar == 0;
         // near ties a sequential run would have met; the other buffer, read
-        // by everyone before this window's exchange, is cleared for the next
-        const int ntie = min(s_ntie[tb], 8);
-        if (tid < ntie && s_tie_j[tb][tid] <= (jstar == UINT_MAX ? W - 1 : jstar)) {
+        // by everyone before this window's exchange, is cleared for the next.
+        // A workgroup that met more ties in the window than it recorded cannot
+        // tell how many of them lie before the first acceptance: the run stops
+        // with an error instead of reporting a count that may be too low.
+        const int ntie_all = s_ntie[tb];
+        if (ntie_all > kTieSlots) {
+            if (tid == 0) raise_err(&ws->err, kErrTieOverflow);
+            alive = false;
+            break;
+        }
+        if (tid < ntie_all && s_tie_j[tb][tid] <= (jstar == UINT_MAX ? W - 1 : jstar)) {
             const unsigned long long slot = atomicAdd((unsigned long long*)&ws->nties, 1ull);
             if (a.ties && st0.near_ties + slot < a.tie_cap)
                 a.ties[st0.near_ties + slot] =
@@ -553,6 +574,10 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         // ------------------------------------------------------------ accept
         const int dstar = (int)(uint32_t)key;
         const uint64_t tstar = t + jstar;
+        // the next window starts at tstar + 1: its temperature is requested now
+        // and used after the update, so that the load's latency is hidden
+        const bool pre = tstar + 1 < t_end;
+        const double T_next = pre ? temperature(temps, T0, tstar + 1) : 0.0;
         uint32_t istar = idx0 + jstar;
         if (istar >= m) istar -= m;
         if (rnd) istar = random_pair_index(seed, chain_id, tstar, m);
@@ -599,17 +624,8 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         self_u = wave_sum(self_u);
         self_v = wave_sum(self_v);
         if (lane == 0) { s_selfw[wave][0] = self_u; s_selfw[wave][1] = self_v; }
-        __syncthreads();   // staged rows complete; everyone has read p
-        if (tid == 0) { lps[u] = (int16_t)pu_new; lps[v] = (int16_t)pv_new; }
-        // own rows of B': rows u, v are replaced (whole rows, all threads), the
-        // others swap columns u, v (thread lr for own row lr, in parallel)
-        for (int which = 0; which < 2; ++which) {
-            const int x = which == 0 ? u : v;
-            if (x % G != w) continue;
-            uint8_t* row = lBb + (x / G) * P;
-            const uint8_t* src = which == 0 ? lTu : lTv;
-            for (int k = tid; k < n; k += nt) row[k] = src[k];
-        }
+        // own rows of B' other than u, v swap columns u, v (thread lr for own
+        // row lr); nothing reads B' between the exchange and the touched pass
         for (int lr = tid; lr < Rw; lr += nt) {
             const int r = w + G * lr;
             if (r != u && r != v) {
@@ -619,9 +635,25 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 row[v] = x;
             }
         }
+        __syncthreads();   // staged rows and B' columns complete; everyone has read p
+        if (tid == 0) { lps[u] = (int16_t)pu_new; lps[v] = (int16_t)pv_new; }
+        // own rows u, v of B' are replaced by the staged rows (whole rows, all
+        // threads); the touched pass below skips them
+        for (int which = 0; which < 2; ++which) {
+            const int x = which == 0 ? u : v;
+            if (x % G != w) continue;
+            uint8_t* row = lBb + (x / G) * P;
+            const uint8_t* src = which == 0 ? lTu : lTv;
+            for (int k = tid; k < n; k += nt) row[k] = src[k];
+        }
         if (nrec == kRec) flush();
-        // (no barrier: the pass below reads neither B' nor p, and the touched
-        // rows, which read B', come after the next one)
+        // No barrier between the correction of the disjoint pairs and the
+        // touched pass: the first reads neither B' nor p and writes Delta only,
+        // the second reads own rows of A and B' other than u, v and the staged
+        // rows and writes its results to s_pub only, so a wave that finishes its
+        // share of the first goes on to its touched row while others still
+        // work.  Columns u, v of Delta take the touched values from s_pub after
+        // the barrier that ends both passes.
 
         // pairs of own rows disjoint from {u, v}: the entries of up to eight
         // own rows in two of this thread's columns are loaded before any is
@@ -671,7 +703,6 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 }
             }
         }
-        __syncthreads();   // columns u, v of own rows are written next
         // Delta(r, u), Delta(r, v) of own rows: one wave per row
         {
             int su = 0, sv = 0;
@@ -699,22 +730,25 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 }
                 const int Pu = wave_sum((int)pu_), Pv = wave_sum((int)pv_), Sr = wave_sum((int)self);
                 if (lane == 0) {
-                    const int du = finish_sym(Pu - Sr - su, arr, aru, sur, suu, brr, bru, tur, tuu);
-                    const int dv = finish_sym(Pv - Sr - sv, arr, arv, svr, svv, brr, brv, tvr, tvv);
-                    lD[lr * n + u] = du;
-                    lD[lr * n + v] = dv;
-                    s_pub[2 * lr] = du;
-                    s_pub[2 * lr + 1] = dv;
+                    s_pub[2 * lr] = finish_sym(Pu - Sr - su, arr, aru, sur, suu, brr, bru, tur, tuu);
+                    s_pub[2 * lr + 1] = finish_sym(Pv - Sr - sv, arr, arv, svr, svv, brr, brv, tvr, tvv);
                 }
             }
         }
-        // publish this workgroup's touched values as one contiguous block; the
-        // stores complete during the next scan
+        // columns u, v of own rows take the touched values, and this
+        // workgroup's touched values are published as one contiguous block;
+        // the stores complete during the next scan.  Rows u, v (if own) keep
+        // whatever the correction wrote: they are stale and refreshed from the
+        // published values in the next exchange.
         __syncthreads();
         {
             unsigned long long* dst = X + ((par * G + w) * Rmax) * 2;
             const unsigned long long tag = (unsigned long long)(uint32_t)epoch << 32;
-            for (int i = tid; i < 2 * Rw; i += nt) put64(dst + i, tag | (uint32_t)s_pub[i]);
+            for (int i = tid; i < 2 * Rw; i += nt) {
+                const int lr = i >> 1, r = w + G * lr;
+                if (r != u && r != v) lD[lr * n + ((i & 1) ? v : u)] = s_pub[i];
+                put64(dst + i, tag | (uint32_t)s_pub[i]);
+            }
         }
         pu = u; pv = v; pd = dstar; ppar = par; ptag = (uint32_t)epoch;
         par ^= 1;
@@ -723,6 +757,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         r0 = u; s0 = v;
         if (++s0 == n) { if (++r0 == n - 1) r0 = 0; s0 = r0 + 1; }
         kwin = a.kmin;
+        if (pre) { bound_next = reject_bound(T_next); bound_ready = true; }
         if (tid == 0) { mark(QAP_PH_DELTA_UPDATE); bump(QAP_PH_N_DELTA_ACC, 1); }
     }
 
@@ -747,7 +782,8 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             st.near_ties = st0.near_ties + __hip_atomic_load((unsigned long long*)&ws->nties, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT);
             st.cost = cost; st.best_cost = best; st.best_iter = best_iter;
-            st.status = alive ? QAP_OK : QAP_E_TIMEOUT;
+            const int err = get(&ws->err);
+            st.status = alive && err == 0 ? QAP_OK : (err == kErrTieOverflow ? QAP_E_TIE_OVERFLOW : QAP_E_TIMEOUT);
             st.mode = QAP_MODE_DELTA;
             *a.state = st;
             mark(QAP_PH_IO);

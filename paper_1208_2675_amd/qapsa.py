@@ -11,7 +11,6 @@ those functions in the order the method needs (set-up, schedule, run).
 from __future__ import annotations
 
 import ctypes as C
-import math
 import os
 
 import numpy as np
@@ -21,8 +20,10 @@ LIB_PATH = os.path.join(_HERE, "libqapsa.so")
 
 QAP_OK, QAP_E_INVAL, QAP_E_NOT_PERM, QAP_E_RANGE = 0, -1, -2, -3
 QAP_E_NOMEM, QAP_E_DEVICE, QAP_E_UNSUPPORTED, QAP_E_STATE, QAP_E_TIMEOUT = -4, -5, -6, -7, -8
+QAP_E_TIE_OVERFLOW = -9
 QAP_MODE_SCRATCH, QAP_MODE_DELTA, QAP_MODE_SCRATCH_STALE = 0, 1, 2
 QAP_FLAG_DELTA_ONLY, QAP_FLAG_SCRATCH_ONLY, QAP_FLAG_MULTI_WG, QAP_FLAG_RANDOM_ORDER = 1, 2, 4, 8
+QAP_FLAG_SINGLE_WG = 16
 
 
 class QapError(RuntimeError):
@@ -92,6 +93,8 @@ def _load():
     L.qap_temp_table_len.restype = u64
     L.qap_schedule_tables.argtypes = [u64, C.c_double, vp, vp]
     L.qap_schedule_tables.restype = C.c_int
+    L.qap_schedule_init.argtypes = [i32, C.POINTER(InstanceInfo), u64, C.c_double, C.POINTER(Schedule)]
+    L.qap_schedule_init.restype = C.c_int
     L.qap_workspace_bytes.argtypes = [i32]
     L.qap_workspace_bytes.restype = u64
     L.qap_sa_run.argtypes = [i32, vp, vp, vp, vp, vp, vp, C.POINTER(Schedule), C.POINTER(InstanceInfo),
@@ -151,6 +154,10 @@ def qap_schedule_tables(iters, alpha, temps, stream=None) -> int:
     return _lib.qap_schedule_tables(iters, alpha, _ptr(temps), _stream(stream))
 
 
+def qap_schedule_init(n, info: InstanceInfo, iters, final_ratio, sched: Schedule) -> int:
+    return _lib.qap_schedule_init(n, C.byref(info), iters, final_ratio, C.byref(sched))
+
+
 def qap_workspace_bytes(n: int) -> int:
     return int(_lib.qap_workspace_bytes(n))
 
@@ -169,9 +176,19 @@ def qap_tabu_run(n, A, Bp, p, delta, state, sched: TabuSchedule, info: InstanceI
 
 # ------------------------------------------------------------- conveniences
 
-def geometric_alpha(iters: int, ratio: float = 1e-3) -> float:
-    """Per-iteration factor of a geometric schedule falling by `ratio` over `iters`."""
-    return 1.0 if iters <= 1 else math.pow(ratio, 1.0 / float(iters - 1))
+def schedule_for(n: int, info: InstanceInfo, iters: int, ratio: float = 1e-3, T0: float | None = None) -> Schedule:
+    """The library's geometric schedule (qap_schedule_init) for an instance
+    whose facts ``info`` came back from qap_delta_init; ``T0`` overrides the
+    start temperature (e.g. +inf, every proposal accepted)."""
+    sched = Schedule()
+    if T0 is not None and info.sum_abs_delta <= 0:
+        # the library refuses T0 = mean |Delta| = 0; an explicit T0 needs only alpha
+        info = InstanceInfo.from_buffer_copy(bytes(info))
+        info.sum_abs_delta = 1
+    _check(qap_schedule_init(n, info, iters, ratio, sched), "qap_schedule_init")
+    if T0 is not None:
+        sched.T0 = float(T0)
+    return sched
 
 
 def _struct_from(t, cls):
@@ -226,11 +243,13 @@ class Chain:
         self.info = _struct_from(self.info_d, InstanceInfo)
         if self.info.status != QAP_OK:
             raise QapError(self.info.status, "qap_delta_init (device)")
-        T0 = self.T0_override if self.T0_override is not None else float(self.info.sum_abs_delta) / float(self.m)
-        alpha = geometric_alpha(self.iters, self.ratio)
-        self.sched = Schedule(self.iters, 0, T0, alpha, self.seed & (2**64 - 1), self.chain_id, self.flags,
-                              self.switch_permille, 0)
-        _check(qap_schedule_tables(self.iters, alpha, self.temps, self.stream), "qap_schedule_tables")
+        self.sched = schedule_for(n, self.info, self.iters, self.ratio, self.T0_override)
+        self.sched.t_end = 0
+        self.sched.seed = self.seed & (2**64 - 1)
+        self.sched.chain_id = self.chain_id
+        self.sched.flags = self.flags
+        self.sched.switch_permille = self.switch_permille
+        _check(qap_schedule_tables(self.iters, self.sched.alpha, self.temps, self.stream), "qap_schedule_tables")
         return self
 
     def buffers(self) -> RunBuffers:
@@ -275,7 +294,10 @@ class Chain:
         nt = min(st.near_ties, self.tie_cap)
         ties = np.frombuffer(self.ties.cpu().numpy().tobytes(), dtype=np.dtype(
             [("t", "<u8"), ("delta", "<i8"), ("z", "<f8")]))[:nt]
-        out["near_tie_t"] = np.sort(ties["t"])
+        order = np.argsort(ties["t"], kind="stable")
+        out["near_tie_t"] = ties["t"][order]
+        out["near_tie_z"] = ties["z"][order]
+        out["near_tie_delta"] = ties["delta"][order]
         out["T0"], out["alpha"] = self.sched.T0, self.sched.alpha
         if with_delta:
             out["delta"] = self.delta.cpu().numpy().astype(np.int64)[: self.m]
@@ -385,10 +407,12 @@ class Batch:
         self.descs = None
         self.scratch = {}
 
-    def init(self, ratio: float = 1e-3, flags: int = 0, switch_permille=0):
+    def init(self, ratio: float = 1e-3, flags: int = 0, switch_permille=0, T0=None):
         """Step (a) of Sec. 2.2 for every chain and the descriptors of the batch.
         ``switch_permille`` is a number or a function (n, symmetric) -> number
-        (a tuned table, see tune.py); 0 means the library default."""
+        (a tuned table, see tune.py); 0 means the library default.  ``T0``
+        (None, a number or a function of the chain index) overrides the start
+        temperature of the library's schedule."""
         torch = self.torch
         i4, i8, f8 = 4, 8, 8
         for i, ch in enumerate(self.chains):
@@ -406,11 +430,10 @@ class Batch:
             if inf.status != QAP_OK:
                 raise QapError(inf.status, f"qap_delta_init (device), chain {i}")
             po, bo, do, to = self.off[i]
-            m = ch.n * (ch.n - 1) // 2
-            T0 = float(inf.sum_abs_delta) / float(m)
-            alpha = geometric_alpha(ch.iters, ratio)
+            T0_i = T0(i) if callable(T0) else T0
+            sc = schedule_for(ch.n, inf, ch.iters, ratio, T0_i)
             temps = self.temps.data_ptr() + f8 * to
-            _check(qap_schedule_tables(ch.iters, alpha, temps), "qap_schedule_tables")
+            _check(qap_schedule_tables(ch.iters, sc.alpha, temps), "qap_schedule_tables")
             A, _ = self.views[i]
             scr = None
             if needs_scratch(ch.n, bool(inf.symmetric), inf.a_max - inf.a_min, inf.b_max - inf.b_min):
@@ -422,7 +445,7 @@ class Batch:
                                  int(sw), A.data_ptr(), self.Bp.data_ptr() + i4 * bo,
                                  self.p.data_ptr() + i4 * po, self.delta.data_ptr() + i4 * do,
                                  self.state_d[i].data_ptr(), temps, self.ties[i].data_ptr(), self.tie_cap,
-                                 ch.chain_id, ch.iters, ch.iters, T0, ch.philox_seed & (2**64 - 1), scr)
+                                 ch.chain_id, ch.iters, ch.iters, sc.T0, ch.philox_seed & (2**64 - 1), scr)
         self.descs = descs
         raw = np.frombuffer(bytes(descs), dtype=np.uint8).copy()
         self.descs_d = torch.from_numpy(raw).to(self.p.device)

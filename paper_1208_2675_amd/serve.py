@@ -72,6 +72,7 @@ class ServerStats:
     iterations: int = 0
     busy_s: float = 0.0
     resident_sum: int = 0
+    max_resident: int = 0
     admitted: int = 0
     waits_for_memory: int = 0
     waits_for_slot: int = 0
@@ -124,9 +125,12 @@ class Server:
         info = Q._struct_from(b["info"], Q.InstanceInfo)
         if info.status != Q.QAP_OK:
             raise Q.QapError(info.status, f"request {rid}")
-        T0 = float(info.sum_abs_delta) / float(m)
-        alpha = Q.geometric_alpha(ch.iters, self.ratio)
-        Q._check(Q.qap_schedule_tables(ch.iters, alpha, b["temps"]), "qap_schedule_tables")
+        sched = Q.schedule_for(n, info, ch.iters, self.ratio)
+        sched.t_end = 0
+        sched.seed = ch.philox_seed & (2**64 - 1)
+        sched.chain_id = ch.chain_id
+        T0 = sched.T0
+        Q._check(Q.qap_schedule_tables(ch.iters, sched.alpha, b["temps"]), "qap_schedule_tables")
         ra, rb = info.a_max - info.a_min, info.b_max - info.b_min
         wide = not Q.fits_one_workgroup(n, bool(info.symmetric), ra, rb)
         scr = b["ws"].data_ptr() if Q.needs_scratch(n, bool(info.symmetric), ra, rb) else None
@@ -136,7 +140,7 @@ class Server:
                            ch.chain_id, ch.iters, ch.iters, T0, ch.philox_seed & (2**64 - 1), scr)
         r = Resident(rid, ch, arrival, now, b, desc, wide)
         r.info = info
-        r.sched = Q.Schedule(ch.iters, 0, T0, alpha, ch.philox_seed & (2**64 - 1), ch.chain_id, 0, 0, 0)
+        r.sched = sched
         return r
 
     def admit(self, now: float):
@@ -195,6 +199,7 @@ class Server:
         self.stats.busy_s += time.perf_counter() - t0
         self.stats.slices += 1
         self.stats.resident_sum += len(self.resident)
+        self.stats.max_resident = max(self.stats.max_resident, len(self.resident))
         return self.retire()
 
     def retire(self) -> list[Result]:

@@ -29,8 +29,8 @@ def qlib():
 def test_header_declares_the_boundary():
     names = set(_declared())
     assert {"qap_strerror", "qap_cost", "qap_delta_init", "qap_temp_table_len", "qap_workspace_bytes",
-            "qap_schedule_tables", "qap_sa_run", "qap_batch_workspace_bytes", "qap_sa_run_batch",
-            "qap_tabu_run"} <= names
+            "qap_schedule_tables", "qap_schedule_init", "qap_sa_run", "qap_batch_workspace_bytes",
+            "qap_sa_run_batch", "qap_tabu_run"} <= names
 
 
 def test_every_declared_symbol_is_exported(qlib):
@@ -85,7 +85,7 @@ def test_host_side_argument_errors(qlib):
                 Q.Schedule(100, 100, float("nan"), 0.99, 1, 0, 0, 0, 0),
                 Q.Schedule(100, 100, 1.0, 1.5, 1, 0, 0, 0, 0), Q.Schedule(0, 0, 1.0, 0.5, 1, 0, 0, 0, 0),
                 Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 7, 0, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 3, 0, 0),
-                Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 16, 0, 0),
+                Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 32, 0, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 4 | 16, 0, 0),
                 Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 0, 1001, 0), Q.Schedule(100, 100, 1.0, 0.5, 1, 0, 0, 0, 1)):
         assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, fake, bad, info, bufs, 0) == Q.QAP_E_INVAL
     assert Q.qap_sa_run(8, fake, fake, None, fake, fake, fake, ok, info, bufs, 0) == Q.QAP_E_INVAL
@@ -114,3 +114,38 @@ def test_host_side_argument_errors(qlib):
     assert Q.qap_delta_init(1, fake, fake, fake, fake, fake, fake, None, 0) == Q.QAP_E_INVAL
     assert Q.qap_schedule_tables(0, 0.5, fake, 0) == Q.QAP_E_INVAL
     assert Q.qap_schedule_tables(10, 1.5, fake, 0) == Q.QAP_E_INVAL
+
+
+@pytest.mark.parametrize("n,sym,seed,iters", [(2, False, 1, 1), (9, True, 2, 1000), (40, False, 3, 10**8),
+                                              (150, False, 4, 10**9)])
+def test_schedule_init_matches_the_oracle(orc, n, sym, seed, iters):
+    """qap_schedule_init (host code of the library) gives the oracle's T0 and
+    alpha bit for bit from the instance facts qap_delta_init reports."""
+    import numpy as np
+    from paper_1208_2675_amd import qapsa as Q
+    rng = np.random.default_rng(seed)
+    A = rng.integers(0, 50, (n, n)).astype(np.int32)
+    B = rng.integers(0, 50, (n, n)).astype(np.int32)
+    if sym:
+        A = np.triu(A, 1); A = (A + A.T).astype(np.int32)
+        B = np.triu(B, 1); B = (B + B.T).astype(np.int32)
+    p = rng.permutation(n).astype(np.int32)
+    ref = orc.schedule(A, B, p, iters)
+    if ref["sum_abs"] == 0:
+        pytest.skip("all swap costs are 0")
+    info = Q.InstanceInfo(orc.cost(A, B, p), ref["sum_abs"], 0, 49, 0, 49, int(sym), 0)
+    sched = Q.Schedule()
+    sched.seed, sched.chain_id, sched.flags = 77, 5, 8
+    assert Q.qap_schedule_init(n, info, iters, 1e-3, sched) == Q.QAP_OK
+    assert sched.T0 == ref["T0"] and sched.alpha == ref["alpha"]
+    assert sched.iters == iters and sched.t_end == iters
+    assert (sched.seed, sched.chain_id, sched.flags) == (77, 5, 8)   # left as the caller set them
+    # argument errors
+    assert Q.qap_schedule_init(1, info, iters, 1e-3, sched) == Q.QAP_E_INVAL
+    assert Q.qap_schedule_init(n, info, 0, 1e-3, sched) == Q.QAP_E_INVAL
+    assert Q.qap_schedule_init(n, info, iters, 0.0, sched) == Q.QAP_E_INVAL
+    assert Q.qap_schedule_init(n, info, iters, 1.5, sched) == Q.QAP_E_INVAL
+    bad = Q.InstanceInfo(0, ref["sum_abs"], 0, 49, 0, 49, 0, Q.QAP_E_RANGE)
+    assert Q.qap_schedule_init(n, bad, iters, 1e-3, sched) == Q.QAP_E_RANGE
+    zero = Q.InstanceInfo(0, 0, 0, 0, 0, 0, 1, 0)
+    assert Q.qap_schedule_init(n, zero, iters, 1e-3, sched) == Q.QAP_E_INVAL

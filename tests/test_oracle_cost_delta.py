@@ -135,3 +135,53 @@ def test_bounds_check(orc):
     assert orc.check_bounds(A, B) == -3
     A = np.arange(16, dtype=np.int32).reshape(4, 4)
     assert orc.check_bounds(A, A) == 0
+
+
+def test_bounds_check_swap_cost_branch_alone(orc):
+    """Values that keep the cost bound n^2 max|A| max|B| < 2^62 but break the
+    swap-cost bound (2n + 8) range(A) range(B) < 2^62: entries of both signs,
+    so the range is twice the magnitude.  With n = 4: 16 m^2 < 2^62 while
+    16 (2m)^2 >= 2^62 for m = 2^28.5 (rounded down)."""
+    m = 379625062
+    A = np.array([[m if (i + j) % 2 else -m for j in range(4)] for i in range(4)], dtype=np.int32)
+    n = 4
+    assert n * n * m * m < 2**62 <= (2 * n + 8) * (2 * m) * (2 * m)
+    assert orc.check_bounds(A, A) == -3
+    # halving the magnitude keeps both bounds
+    assert orc.check_bounds(A // 2, A // 2) == 0
+    # one sign only: the range equals the magnitude, both bounds hold
+    assert orc.check_bounds(np.abs(A), np.abs(A)) == 0
+
+
+@pytest.mark.parametrize("n,sym,seed", [(2, False, 1), (5, True, 2), (9, False, 3), (23, True, 4)])
+def test_mean_abs_delta_by_definition(orc, n, sym, seed):
+    """T0 of the schedule is the mean of |C(p o (r s)) - C(p)| over the
+    n(n-1)/2 pairs r < s, each swap cost taken from two evaluations of Eq. (1)
+    (numpy here), averaged with one binary64 division of the integer sum."""
+    rng = np.random.default_rng(seed)
+    A = rng.integers(-5, 30, (n, n)).astype(np.int32)
+    B = rng.integers(-5, 30, (n, n)).astype(np.int32)
+    if sym:
+        A = np.triu(A, 1); A = (A + A.T).astype(np.int32)
+        B = np.triu(B, 1); B = (B + B.T).astype(np.int32)
+    p = rng.permutation(n).astype(np.int32)
+
+    def eq1(q):
+        return int((A.astype(np.int64) * B.astype(np.int64)[np.ix_(q, q)]).sum())
+
+    total = 0
+    pairs = 0
+    for r in range(n):
+        for s in range(r + 1, n):
+            q = p.copy()
+            q[[r, s]] = q[[s, r]]
+            total += abs(eq1(q) - eq1(p))
+            pairs += 1
+    assert pairs == n * (n - 1) // 2
+    T0, sabs = orc.mean_abs_delta(n, orc.delta_matrix(A, B, p))
+    assert sabs == total
+    assert T0 == total / pairs
+    sched = orc.schedule(A, B, p, 1000)
+    assert sched["T0"] == total / pairs and sched["sum_abs"] == total
+    if total:   # a wrong divisor would show: n(n-1) or n^2 pairs instead of n(n-1)/2
+        assert T0 != total / (n * (n - 1)) and T0 != total / (n * n)
