@@ -286,6 +286,33 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
                        const qap_instance_info* info, const qap_run_buffers* bufs,
                        hipStream_t stream);
 
+/* ------------------------------------------------------ no-allocation run */
+
+/* Bytes of the library's static device scratch (1 MiB per device). */
+QAP_API uint64_t qap_static_scratch_bytes(void);
+
+/*
+ * qap_sa_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same run, identical results, but the workspace of the kernels that need one
+ * (the multi-workgroup exchange area, the per-chain scratch of a one-workgroup
+ * chain whose matrices outgrow LDS) is a device array inside the library,
+ * qap_static_scratch_bytes() bytes, one per device, held until the process
+ * ends.  Nothing is allocated on any call.
+ *   arguments  as for qap_sa_run; bufs->workspace must be NULL and
+ *              bufs->workspace_bytes 0 (QAP_E_INVAL otherwise)
+ * Returns QAP_E_NOMEM, before any device work, when the chosen kernel needs
+ * more workspace than the static scratch holds (symmetric multi-workgroup
+ * chains fit at every size the kernel takes; one-workgroup chains with device
+ * scratch up to about 500 facilities), and what qap_sa_run returns otherwise.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents (each kernel initialises what it reads): calls that overlap
+ * on one device, on any streams, race and give wrong results.  Order them.
+ */
+QAP_API int qap_sa_run_static(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int32_t* p,
+                              int32_t* delta, qap_chain_state* state, const qap_schedule* sched,
+                              const qap_instance_info* info, const qap_run_buffers* bufs, hipStream_t stream);
+
 /* ------------------------------------------------------------- tabu search */
 
 /* Schedule of a tabu search (host struct). */

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "qapsa_device.hpp"
 #include "qapsa_internal.hpp"
 
@@ -137,8 +139,16 @@ QAP_API int qap_schedule_init(int32_t n, const qap_instance_info* info, uint64_t
 
 namespace {
 
+// No-allocation variant of qap_sa_run: this file-scope device array replaces
+// the caller's workspace.  Each device holds its own copy until the process
+// ends; host code never passes the array's name to a kernel, only the address
+// hipGetSymbolAddress returns for the current device (looked up once per
+// device, below).
+constexpr size_t kStaticScratchBytes = 1u << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 // Kernel selection and launch of one chain's run; the workspace comes from
-// bufs.
+// bufs (qap_sa_run) or from the library's static scratch (qap_sa_run_static).
 // A workspace smaller than the chosen kernel needs is reported as ws_short.
 int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int32_t* p, int32_t* delta,
                 qap_chain_state* state, const qap_schedule* sched, const qap_instance_info* info,
@@ -239,6 +249,24 @@ int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int3
     return launch_chain_lds(a, sym, a_lds, threads, stream);
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+int static_scratch(void** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return QAP_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return QAP_E_DEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return QAP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -250,6 +278,24 @@ QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* B
     if (n < 2 || n > 46340 || !A || !B || !Bp || !p || !delta || !state || !info || !bufs || !bufs->temps)
         return QAP_E_INVAL;
     return sa_run_impl(n, A, B, Bp, p, delta, state, sched, info, bufs, stream, QAP_E_INVAL);
+}
+
+QAP_API uint64_t qap_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+QAP_API int qap_sa_run_static(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int32_t* p,
+                              int32_t* delta, qap_chain_state* state, const qap_schedule* sched,
+                              const qap_instance_info* info, const qap_run_buffers* bufs, hipStream_t stream)
+{
+    if (n < 2 || n > 46340 || !A || !B || !Bp || !p || !delta || !state || !info || !bufs || !bufs->temps)
+        return QAP_E_INVAL;
+    if (bufs->workspace || bufs->workspace_bytes) return QAP_E_INVAL;
+    void* ws = nullptr;
+    const int rc = static_scratch(&ws);
+    if (rc != QAP_OK) return rc;
+    qap_run_buffers b = *bufs;
+    b.workspace = ws;
+    b.workspace_bytes = kStaticScratchBytes;
+    return sa_run_impl(n, A, B, Bp, p, delta, state, sched, info, &b, stream, QAP_E_NOMEM);
 }
 
 QAP_API uint64_t qap_batch_workspace_bytes(void) { return sizeof(BatchWs); }

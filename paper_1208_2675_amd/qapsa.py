@@ -100,6 +100,10 @@ def _load():
     L.qap_sa_run.argtypes = [i32, vp, vp, vp, vp, vp, vp, C.POINTER(Schedule), C.POINTER(InstanceInfo),
                              C.POINTER(RunBuffers), vp]
     L.qap_sa_run.restype = C.c_int
+    L.qap_sa_run_static.argtypes = L.qap_sa_run.argtypes
+    L.qap_sa_run_static.restype = C.c_int
+    L.qap_static_scratch_bytes.argtypes = []
+    L.qap_static_scratch_bytes.restype = u64
     L.qap_tabu_run.argtypes = [i32, vp, vp, vp, vp, vp, C.POINTER(TabuSchedule), C.POINTER(InstanceInfo), vp,
                                C.POINTER(RunBuffers), vp]
     L.qap_tabu_run.restype = C.c_int
@@ -166,6 +170,16 @@ def qap_sa_run(n, A, B, Bp, p, delta, state, sched: Schedule, info: InstanceInfo
                stream=None) -> int:
     return _lib.qap_sa_run(n, _ptr(A), _ptr(B), _ptr(Bp), _ptr(p), _ptr(delta), _ptr(state), C.byref(sched),
                            C.byref(info), C.byref(bufs), _stream(stream))
+
+
+def qap_sa_run_static(n, A, B, Bp, p, delta, state, sched: Schedule, info: InstanceInfo, bufs: RunBuffers,
+                      stream=None) -> int:
+    return _lib.qap_sa_run_static(n, _ptr(A), _ptr(B), _ptr(Bp), _ptr(p), _ptr(delta), _ptr(state),
+                                  C.byref(sched), C.byref(info), C.byref(bufs), _stream(stream))
+
+
+def qap_static_scratch_bytes() -> int:
+    return int(_lib.qap_static_scratch_bytes())
 
 
 def qap_tabu_run(n, A, Bp, p, delta, state, sched: TabuSchedule, info: InstanceInfo, tabu, bufs: RunBuffers,
@@ -263,8 +277,16 @@ class Chain:
         v = self.prof.cpu().numpy().tolist()
         return {k: int(x) for k, x in zip(PHASES, v)}
 
-    def run(self, t_end: int | None = None):
+    def run(self, t_end: int | None = None, static: bool = False):
+        """Advance the chain to t_end; ``static`` runs through qap_sa_run_static
+        (the library's own device scratch instead of this chain's workspace)."""
         self.sched.t_end = self.iters if t_end is None else int(t_end)
+        if static:
+            bufs = self.buffers()
+            bufs.workspace, bufs.workspace_bytes = None, 0
+            _check(qap_sa_run_static(self.n, self.A, self.B, self.Bp, self.p, self.delta, self.state_d, self.sched,
+                                     self.info, bufs, self.stream), "qap_sa_run_static")
+            return self
         _check(qap_sa_run(self.n, self.A, self.B, self.Bp, self.p, self.delta, self.state_d, self.sched,
                           self.info, self.buffers(), self.stream), "qap_sa_run")
         return self

@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     names = set(_declared())
     assert {"qap_strerror", "qap_cost", "qap_delta_init", "qap_temp_table_len", "qap_workspace_bytes",
             "qap_schedule_tables", "qap_schedule_init", "qap_sa_run", "qap_batch_workspace_bytes",
-            "qap_sa_run_batch", "qap_tabu_run"} <= names
+            "qap_sa_run_batch", "qap_tabu_run", "qap_sa_run_static", "qap_static_scratch_bytes"} <= names
 
 
 def test_every_declared_symbol_is_exported(qlib):
