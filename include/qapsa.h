@@ -132,8 +132,8 @@ typedef struct {
    costs; the flags only pin the mode. */
 #define QAP_FLAG_DELTA_ONLY 1u    /* keep the Delta matrix from the first iteration (Sec. 2.2) */
 #define QAP_FLAG_SCRATCH_ONLY 2u  /* never build the Delta matrix during the run              */
-#define QAP_FLAG_MULTI_WG 4u      /* symmetric byte-valued instances: run on the multi-workgroup
-                                     kernel even where one workgroup could hold the chain
+#define QAP_FLAG_MULTI_WG 4u      /* byte-valued instances: run on the multi-workgroup kernel
+                                     even where one workgroup could hold the chain
                                      (qap_sa_run only; the result is the same)                */
 #define QAP_FLAG_RANDOM_ORDER 8u  /* propose the pairs at random instead of in row-major order
                                      (Sec. 2.1): iteration t proposes pair number
@@ -214,9 +214,10 @@ QAP_API int qap_delta_init(int32_t n, const int32_t* A, const int32_t* B, const 
                            qap_chain_state* state, hipStream_t stream);
 
 /* Bytes of device workspace a run of an n-facility instance may need
-   (qap_run_buffers.workspace): the larger of the multi-workgroup exchange area
-   (49216 + 32 n) and the one-workgroup scratch for asymmetric chains
-   (qap_chain_scratch_bytes(n, 0)). */
+   (qap_run_buffers.workspace): the larger of the multi-workgroup area (the
+   exchange slots and published values, 49216 + 32 n rounded up to 256, plus
+   for asymmetric instances byte copies of A, A^T and B^T, 3 n * 4 ceil(n/4))
+   and the one-workgroup scratch for asymmetric chains (qap_chain_scratch_bytes(n, 0)). */
 QAP_API uint64_t qap_workspace_bytes(int32_t n);
 
 /* Number of doubles in the temperature table of a schedule of `iters` iterations:
@@ -274,12 +275,15 @@ QAP_API int qap_schedule_init(int32_t n, const qap_instance_info* info, uint64_t
  * multi-workgroup and 16-bit kernels need a current Delta and fail with
  * QAP_E_STATE on a stale one.  The run is identical whatever the split of
  * [0, iters) into calls and whichever mode is active.
- * Kernels: one workgroup holds the chain when its matrices fit one CU's LDS;
- * otherwise (symmetric instances up to about 2600 facilities) the chain
- * is spread over many workgroups of one cooperative launch, which needs
- * bufs->workspace; larger ones that qap_single_workgroup accepts run on one
- * workgroup with Delta, A and B' in bufs->workspace.  Returns QAP_E_UNSUPPORTED when no kernel of this build
- * handles n and the value ranges, QAP_E_RANGE when info->status says so.
+ * Kernels: one workgroup holds the chain when its B' fits one CU's LDS
+ * (Delta and then A moving to device memory first); otherwise (symmetric
+ * instances up to about 2600 facilities, asymmetric ones up to about 2000)
+ * the chain is spread over many workgroups of one cooperative launch, which
+ * needs bufs->workspace; larger ones that qap_single_workgroup accepts run on
+ * one workgroup with Delta, A and B' in bufs->workspace.  QAP_FLAG_MULTI_WG
+ * and QAP_FLAG_SINGLE_WG override the choice where the other kernel can take
+ * the chain.  Returns QAP_E_UNSUPPORTED when no kernel of this build handles n
+ * and the value ranges, QAP_E_RANGE when info->status says so.
  */
 QAP_API int qap_sa_run(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int32_t* p, int32_t* delta,
                        qap_chain_state* state, const qap_schedule* sched,

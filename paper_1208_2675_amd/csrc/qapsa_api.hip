@@ -97,7 +97,7 @@ QAP_API uint64_t qap_temp_table_len(uint64_t iters) { return temp_table_len(iter
 QAP_API uint64_t qap_workspace_bytes(int32_t n)
 {
     if (n < 2) return 0;
-    size_t bytes = dist_ws_bytes(n);
+    size_t bytes = dist_ws_bytes(n, false);
     for (int sym = 0; sym < 2; ++sym) {
         const int place = wg_place(n, sym != 0);
         if (place >= 0) {
@@ -180,12 +180,13 @@ int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int3
 
     // byte-valued kernel: value ranges of A and B fit 0..255 after shifting
     const bool bytes_ok = (int64_t)info->a_max - info->a_min <= 255 && (int64_t)info->b_max - info->b_min <= 255;
-    const bool multi = (sched->flags & QAP_FLAG_MULTI_WG) != 0 && sym;
+    const bool multi = (sched->flags & QAP_FLAG_MULTI_WG) != 0;
     const bool single = (sched->flags & QAP_FLAG_SINGLE_WG) != 0;
     a.flags &= ~(QAP_FLAG_MULTI_WG | QAP_FLAG_SINGLE_WG);
     int place = bytes_ok && !multi ? wg_place(n, sym) : -1;
-    // large symmetric chains: many workgroups share the Delta update, unless one is asked for
-    if (sym && place == 3 && !single) place = -1;
+    // large chains (all their matrices outside LDS on one workgroup): many
+    // workgroups share the Delta update, unless one is asked for
+    if (place == 3 && !single) place = -1;
     // one workgroup: Delta, then A, then B' in device memory where LDS runs out
     if (place >= 0 && place <= 1) return launch_chain_wg(a, sym, place, stream);
     if (place >= 2) {
@@ -194,8 +195,8 @@ int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int3
         a.gscratch = bufs->workspace;
         return launch_chain_wg(a, sym, place, stream);
     }
-    // many workgroups, one cooperative launch: symmetric byte-valued instances
-    if (bytes_ok && sym && !single) {
+    // many workgroups, one cooperative launch: byte-valued instances
+    if (bytes_ok && !single) {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -203,10 +204,10 @@ int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int3
         int G = (n + 7) / 8;                 // about eight rows per workgroup
         if (G > cus) G = cus;
         if (G < 2) G = 2;
-        while (G < cus && lds_dist_bytes(n, G) > budget) ++G;
-        if (lds_dist_bytes(n, G) <= budget) {
+        while (G < cus && lds_dist_bytes(n, G, sym) > budget) ++G;
+        if (lds_dist_bytes(n, G, sym) <= budget) {
             if (!bufs->workspace) return QAP_E_INVAL;
-            if (bufs->workspace_bytes < dist_ws_bytes(n)) return ws_short;
+            if (bufs->workspace_bytes < dist_ws_bytes(n, sym)) return ws_short;
             DistArgs d{};
             d.n = n;
             d.a_min = info->a_min;
@@ -226,7 +227,14 @@ int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int3
             d.ws = (DistWs*)bufs->workspace;
             d.slots = dist_slots(bufs->workspace);
             d.X = dist_X(bufs->workspace);
-            return launch_chain_dist(d, G, 512, stream);
+            if (!sym) {
+                uint8_t* bytes = dist_bytes(bufs->workspace, n);
+                const size_t plane = (size_t)n * dist_pitch(n);
+                d.Ab = bytes;
+                d.Atb = bytes + plane;
+                d.Btb = bytes + 2 * plane;
+            }
+            return launch_chain_dist(d, sym, G, 512, stream);
         }
         // beyond the multi-workgroup kernel's LDS budget: one workgroup with
         // Delta, A and B' in device memory

@@ -84,6 +84,20 @@ __device__ __forceinline__ void pair_of_u(int n, uint32_t idx, int& r, int& s)
     s = lo + 1 + (int)(idx - rs32(n, lo));
 }
 
+// Swap cost of (r, s) from the all-k sums S over rows and columns (general
+// form): the k = r and k = s terms are dropped and the two terms of Eq. (1)
+// with both indices in {r, s} are added.  Arguments are shifted entries at
+// (r,r), (r,s), (s,r), (s,s) of A and B'.
+__device__ __forceinline__ int finish_gen(int S, int arr, int ars, int asr, int ass, int brr, int brs, int bsr, int bss)
+{
+    const int corner = (arr - ass) * (bss - brr) + (ars - asr) * (bsr - brs);
+    const int row_r = (arr - asr) * (bsr - brr);
+    const int row_s = (ars - ass) * (bss - brs);
+    const int col_r = (arr - ars) * (brs - brr);
+    const int col_s = (asr - ass) * (bss - bsr);
+    return S - row_r - row_s - col_r - col_s + corner;
+}
+
 __device__ __forceinline__ int finish_sym(int S, int arr, int ars, int asr, int ass, int brr, int brs, int bsr, int bss)
 {
     const int corner = (arr - ass) * (bss - brr) + (ars - asr) * (bsr - brs);
@@ -108,37 +122,52 @@ __device__ __forceinline__ void raise_err(int* p, int code)
 
 struct Lds {
     int32_t* D;      // [R][n] full rows of Delta
-    uint8_t* Ab;     // [R][P] rows of A - a_min
+    uint8_t* Ab;     // [R][P] rows of A - a_min (symmetric form; the general form reads A from device memory)
     uint8_t* Bb;     // [R][P] rows of B' - b_min
+    uint8_t* Bt;     // [R][P] columns of B' - b_min (general form)
     uint8_t* Su;     // [P] row u of A - a_min
     uint8_t* Sv;
     uint8_t* Tu;     // [P] row u of B' - b_min after the swap
     uint8_t* Tv;
-    uint32_t* abp;   // [n] (A[u][k]-A[v][k]) twice, as int16 pair
-    uint32_t* bbp;   // [n] (B'[u][k]-B'[v][k]) twice
+    uint8_t* Scu;    // [P] column u of A - a_min (general form)
+    uint8_t* Scv;
+    uint8_t* Tcu;    // [P] column u of B' - b_min after the swap (general form)
+    uint8_t* Tcv;
+    uint32_t* abp;   // [n] int16 pair: (A[k][u]-A[k][v], A[u][k]-A[v][k]), equal halves when symmetric
+    uint32_t* bbp;   // [n] int16 pair: (B'[k][u]-B'[k][v], B'[u][k]-B'[v][k]) after the swap
     int16_t* ps;     // [n]
 };
 
 __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-__host__ __device__ inline size_t dist_layout(int n, int G, int q, char* base, Lds* L)
+// LDS layout of one workgroup.  The general (asymmetric) form keeps its own
+// columns of B' beside its rows and stages columns u, v as well as rows; its
+// rows and columns of A are read from byte copies in device memory instead
+// (they never change), so that N = 2000 still fits one CU's LDS.
+__host__ __device__ inline size_t dist_layout(int n, int G, int q, bool sym, char* base, Lds* L)
 {
     const size_t R = (size_t)(n + G - 1) / G, P = 4 * (size_t)q;
     size_t off = 0;
     auto take = [&](size_t b) { char* p = base ? base + off : nullptr; off = a16(off + b); return p; };
     char* d = take(4 * R * n);
-    char* ab = take(R * P);
+    char* ab = sym ? take(R * P) : nullptr;
     char* bb = take(R * P);
+    char* bt = sym ? nullptr : take(R * P);
     char* su = take(P);
     char* sv = take(P);
     char* tu = take(P);
     char* tv = take(P);
+    char* scu = sym ? nullptr : take(P);
+    char* scv = sym ? nullptr : take(P);
+    char* tcu = sym ? nullptr : take(P);
+    char* tcv = sym ? nullptr : take(P);
     char* abp = take(4 * (size_t)n);
     char* bbp = take(4 * (size_t)n);
     char* ps = take(2 * (size_t)n);
     if (L) {
-        L->D = (int32_t*)d; L->Ab = (uint8_t*)ab; L->Bb = (uint8_t*)bb;
+        L->D = (int32_t*)d; L->Ab = (uint8_t*)ab; L->Bb = (uint8_t*)bb; L->Bt = (uint8_t*)bt;
         L->Su = (uint8_t*)su; L->Sv = (uint8_t*)sv; L->Tu = (uint8_t*)tu; L->Tv = (uint8_t*)tv;
+        L->Scu = (uint8_t*)scu; L->Scv = (uint8_t*)scv; L->Tcu = (uint8_t*)tcu; L->Tcv = (uint8_t*)tcv;
         L->abp = (uint32_t*)abp; L->bbp = (uint32_t*)bbp; L->ps = (int16_t*)ps;
     }
     return off;
@@ -203,6 +232,7 @@ __device__ __noinline__ bool exact_test(int d, const double* temps, double T0, u
     return metropolis_positive(d, temperature(temps, T0, t), uniform_r(seed, chain, t), z);
 }
 
+template <bool SYM>
 __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
 {
     extern __shared__ __align__(16) char smem[];
@@ -226,15 +256,24 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     const int C = Rw;                             // columns s = w + G c of this workgroup (same count)
     const uint32_t m = (uint32_t)((int64_t)n * (n - 1) / 2);
     Lds L_;
-    dist_layout(n, G, q, smem, &L_);
+    dist_layout(n, G, q, SYM, smem, &L_);
     // the LDS arrays as plain pointer values
     int32_t* const lD = L_.D;
     uint8_t* const lAb = L_.Ab;
     uint8_t* const lBb = L_.Bb;
+    uint8_t* const lBt = L_.Bt;
     uint8_t* const lSu = L_.Su;
     uint8_t* const lSv = L_.Sv;
     uint8_t* const lTu = L_.Tu;
     uint8_t* const lTv = L_.Tv;
+    uint8_t* const lScu = L_.Scu;
+    uint8_t* const lScv = L_.Scv;
+    uint8_t* const lTcu = L_.Tcu;
+    uint8_t* const lTcv = L_.Tcv;
+    // general form: byte copies (value - minimum, rows padded to P) in device memory
+    const uint8_t* __restrict__ const gA = a.Ab;     // A
+    const uint8_t* __restrict__ const gAt = a.Atb;   // A^T
+    const uint8_t* __restrict__ const gBt = a.Btb;   // B^T
     uint32_t* const labp = L_.abp;
     uint32_t* const lbbp = L_.bbp;
     int16_t* const lps = L_.ps;
@@ -269,17 +308,22 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             lD[lr * n + s] = d;
         }
         for (int k = tid; k < P; k += nt) {
-            int av = 0, bv = 0;
+            int av = 0, bv = 0, cv = 0;
             if (k < n) {
                 av = a.A[r * n + k] - a.a_min;
                 bv = a.Bp[r * n + k] - a.b_min;
-                if ((av | bv) & ~0xff) s_ok = 0;
+                if (!SYM) cv = a.Bp[k * n + r] - a.b_min;   // column r of B'
+                if ((av | bv | cv) & ~0xff) s_ok = 0;
             }
-            lAb[lr * P + k] = (uint8_t)av;
+            if constexpr (SYM) lAb[lr * P + k] = (uint8_t)av;
             lBb[lr * P + k] = (uint8_t)bv;
+            if constexpr (!SYM) lBt[lr * P + k] = (uint8_t)cv;
         }
     }
-    for (int k = tid; k < P; k += nt) { lSu[k] = 0; lSv[k] = 0; lTu[k] = 0; lTv[k] = 0; }
+    for (int k = tid; k < P; k += nt) {
+        lSu[k] = 0; lSv[k] = 0; lTu[k] = 0; lTv[k] = 0;
+        if constexpr (!SYM) { lScu[k] = 0; lScv[k] = 0; lTcu[k] = 0; lTcv[k] = 0; }
+    }
     for (int i = tid; i < n; i += nt) {
         const int pi = a.p[i];
         if (pi < 0 || pi >= n) s_ok = 0;   // p indexes B below
@@ -326,7 +370,10 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     // A[v][.], B'[u][.] = B[p(v)][p(.)] and B'[v][.] = B[p(u)][p(.)], this
     // thread's columns, all loads issued before any result is used.
     const int nk = (n + nt - 1) / nt;   // columns per thread (uniform)
-    auto stage_loads = [&](int u, int v, int* ga, int* gb, int* gc, int* gd) __attribute__((always_inline)) {
+    // The general form also stages columns u, v of A and of B': their shifted
+    // bytes, packed four to a register (A[k][u], A[k][v], B'[k][u], B'[k][v]).
+    auto stage_loads = [&](int u, int v, int* ga, int* gb, int* gc, int* gd, uint32_t* ge)
+        __attribute__((always_inline)) {
         const int pu_new = uni((int)lps[v]), pv_new = uni((int)lps[u]);
 #pragma unroll
         for (int i = 0; i < kMaxPerThread; ++i) {
@@ -337,6 +384,10 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             gb[i] = a.A[v * n + k];
             gc[i] = a.B[pu_new * n + pk];
             gd[i] = a.B[pv_new * n + pk];
+            if constexpr (!SYM) {
+                ge[i] = (uint32_t)gAt[(size_t)u * P + k] | ((uint32_t)gAt[(size_t)v * P + k] << 8) |
+                        ((uint32_t)gBt[(size_t)pu_new * P + pk] << 16) | ((uint32_t)gBt[(size_t)pv_new * P + pk] << 24);
+            }
         }
     };
     // Speculative staging: while the previous window accepted its first
@@ -346,6 +397,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     // that proposal is the one accepted, and requested again otherwise.
     bool last_j0 = false;
     int ga[kMaxPerThread], gb[kMaxPerThread], gc[kMaxPerThread], gd[kMaxPerThread];
+    uint32_t ge[kMaxPerThread];
 
     // Stale own rows take the published Delta(., u), Delta(., v) of the last
     // swap.  Each published value carries the tag of the update that wrote it,
@@ -390,7 +442,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         const unsigned long long tag = (epoch & 1023ull) << 54;
         unsigned long long* slots = slot_base + (epoch & 1) * kMaxGroups;
         if (wave != 0) {
-            if (spec) stage_loads(r0, s0, ga, gb, gc, gd);
+            if (spec) stage_loads(r0, s0, ga, gb, gc, gd, ge);
             refresh_part(tid - 64, nt - 64);
         }
         if (wave == 0) {
@@ -400,7 +452,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             wk = wave_min_u64(wk);
             const unsigned long long own = wk == ~0ull ? kNone : (wk & kKeyBits);
             if (lane == 0) put64(&slots[w], tag | own);
-            if (spec) stage_loads(r0, s0, ga, gb, gc, gd);
+            if (spec) stage_loads(r0, s0, ga, gb, gc, gd, ge);
             uint64_t spins = 0;
             bool ok = true;
             unsigned long long best_key;
@@ -600,7 +652,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         // staged rows after the swap (requested during the exchange when the
         // accepted proposal is the window's first and that was speculated)
         const int pu_new = uni((int)lps[v]), pv_new = uni((int)lps[u]);
-        if (!(spec && jstar == 0)) stage_loads(u, v, ga, gb, gc, gd);
+        if (!(spec && jstar == 0)) stage_loads(u, v, ga, gb, gc, gd, ge);
         // staged bytes, packed differences and this thread's share of the self
         // terms <A[x][.], B'[x][.]> of x = u, v
         int self_u = 0, self_v = 0;
@@ -615,10 +667,24 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 lTu[k] = (uint8_t)tu;
                 lTv[k] = (uint8_t)tv;
                 const int da = su - sv, db = tu - tv;
-                labp[k] = (uint32_t)(uint16_t)da | ((uint32_t)(uint16_t)da << 16);
-                lbbp[k] = (uint32_t)(uint16_t)db | ((uint32_t)(uint16_t)db << 16);
-                self_u += su * tu;
-                self_v += sv * tv;
+                if constexpr (SYM) {
+                    labp[k] = (uint32_t)(uint16_t)da | ((uint32_t)(uint16_t)da << 16);
+                    lbbp[k] = (uint32_t)(uint16_t)db | ((uint32_t)(uint16_t)db << 16);
+                    self_u += su * tu;
+                    self_v += sv * tv;
+                } else {
+                    const int cu = ge[i] & 0xff, cv = (ge[i] >> 8) & 0xff;
+                    const int tcu = (ge[i] >> 16) & 0xff, tcv = ge[i] >> 24;
+                    lScu[k] = (uint8_t)cu;
+                    lScv[k] = (uint8_t)cv;
+                    lTcu[k] = (uint8_t)tcu;
+                    lTcv[k] = (uint8_t)tcv;
+                    const int dc = cu - cv, dt = tcu - tcv;
+                    labp[k] = (uint32_t)(uint16_t)dc | ((uint32_t)(uint16_t)da << 16);
+                    lbbp[k] = (uint32_t)(uint16_t)dt | ((uint32_t)(uint16_t)db << 16);
+                    self_u += su * tu + cu * tcu;
+                    self_v += sv * tv + cv * tcv;
+                }
             }
         }
         self_u = wave_sum(self_u);
@@ -633,6 +699,12 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 const uint8_t x = row[u];
                 row[u] = row[v];
                 row[v] = x;
+                if constexpr (!SYM) {   // column r of B': its entries u, v change places too
+                    uint8_t* col = lBt + lr * P;
+                    const uint8_t y = col[u];
+                    col[u] = col[v];
+                    col[v] = y;
+                }
             }
         }
         __syncthreads();   // staged rows and B' columns complete; everyone has read p
@@ -645,6 +717,11 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             uint8_t* row = lBb + (x / G) * P;
             const uint8_t* src = which == 0 ? lTu : lTv;
             for (int k = tid; k < n; k += nt) row[k] = src[k];
+            if constexpr (!SYM) {
+                uint8_t* col = lBt + (x / G) * P;
+                const uint8_t* srcc = which == 0 ? lTcu : lTcv;
+                for (int k = tid; k < n; k += nt) col[k] = srcc[k];
+            }
         }
         if (nrec == kRec) flush();
         // No barrier between the correction of the disjoint pairs and the
@@ -712,26 +789,51 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             for (int lr = wave; lr < Rw; lr += nwaves) {
                 const int r = w + G * lr;
                 if (r == u || r == v) continue;
-                const uint32_t* ar = (const uint32_t*)(lAb + lr * P);
+                // own row r of A: LDS (symmetric form) or the byte copy in device memory
+                const uint8_t* A_r = SYM ? lAb + lr * P : gA + (size_t)r * P;
+                const uint32_t* ar = (const uint32_t*)A_r;
                 const uint32_t* br = (const uint32_t*)(lBb + lr * P);
-                const uint8_t* A_r = lAb + lr * P;
                 const uint8_t* B_r = lBb + lr * P;
                 const int arr = A_r[r], aru = A_r[u], arv = A_r[v], brr = B_r[r], bru = B_r[u], brv = B_r[v];
                 const int sur = lSu[r], suu = lSu[u], svr = lSv[r], svv = lSv[v];
                 const int tur = lTu[r], tuu = lTu[u], tvr = lTv[r], tvv = lTv[v];
                 uint32_t pu_ = 0, pv_ = 0, self = 0;
-                for (int k = lane; k < q; k += 64) {
-                    const uint32_t xa = ar[k], xb = br[k];
-                    pu_ = dot4(xa, ((const uint32_t*)lTu)[k], pu_);
-                    pu_ = dot4(((const uint32_t*)lSu)[k], xb, pu_);
-                    pv_ = dot4(xa, ((const uint32_t*)lTv)[k], pv_);
-                    pv_ = dot4(((const uint32_t*)lSv)[k], xb, pv_);
-                    self = dot4(xa, xb, self);
+                if constexpr (SYM) {
+                    for (int k = lane; k < q; k += 64) {
+                        const uint32_t xa = ar[k], xb = br[k];
+                        pu_ = dot4(xa, ((const uint32_t*)lTu)[k], pu_);
+                        pu_ = dot4(((const uint32_t*)lSu)[k], xb, pu_);
+                        pv_ = dot4(xa, ((const uint32_t*)lTv)[k], pv_);
+                        pv_ = dot4(((const uint32_t*)lSv)[k], xb, pv_);
+                        self = dot4(xa, xb, self);
+                    }
+                } else {
+                    // rows and columns: column r of A from the copy of A^T, column r of B' in LDS
+                    const uint32_t* cr = (const uint32_t*)(gAt + (size_t)r * P);
+                    const uint32_t* dr = (const uint32_t*)(lBt + lr * P);
+                    for (int k = lane; k < q; k += 64) {
+                        const uint32_t xa = ar[k], xb = br[k], xc = cr[k], xd = dr[k];
+                        pu_ = dot4(xa, ((const uint32_t*)lTu)[k], pu_);
+                        pu_ = dot4(((const uint32_t*)lSu)[k], xb, pu_);
+                        pu_ = dot4(xc, ((const uint32_t*)lTcu)[k], pu_);
+                        pu_ = dot4(((const uint32_t*)lScu)[k], xd, pu_);
+                        pv_ = dot4(xa, ((const uint32_t*)lTv)[k], pv_);
+                        pv_ = dot4(((const uint32_t*)lSv)[k], xb, pv_);
+                        pv_ = dot4(xc, ((const uint32_t*)lTcv)[k], pv_);
+                        pv_ = dot4(((const uint32_t*)lScv)[k], xd, pv_);
+                        self = dot4(xa, xb, self);
+                        self = dot4(xc, xd, self);
+                    }
                 }
                 const int Pu = wave_sum((int)pu_), Pv = wave_sum((int)pv_), Sr = wave_sum((int)self);
                 if (lane == 0) {
-                    s_pub[2 * lr] = finish_sym(Pu - Sr - su, arr, aru, sur, suu, brr, bru, tur, tuu);
-                    s_pub[2 * lr + 1] = finish_sym(Pv - Sr - sv, arr, arv, svr, svv, brr, brv, tvr, tvv);
+                    if constexpr (SYM) {
+                        s_pub[2 * lr] = finish_sym(Pu - Sr - su, arr, aru, sur, suu, brr, bru, tur, tuu);
+                        s_pub[2 * lr + 1] = finish_sym(Pv - Sr - sv, arr, arv, svr, svv, brr, brv, tvr, tvv);
+                    } else {
+                        s_pub[2 * lr] = finish_gen(Pu - Sr - su, arr, aru, sur, suu, brr, bru, tur, tuu);
+                        s_pub[2 * lr + 1] = finish_gen(Pv - Sr - sv, arr, arv, svr, svv, brr, brv, tvr, tvv);
+                    }
                 }
             }
         }
@@ -809,25 +911,54 @@ __global__ void k_ws_reset(DistWs* ws, unsigned long long* slots, unsigned long 
     }
 }
 
+// General form: byte copies (value - minimum) of A, A^T and B^T with rows
+// padded to P bytes (zeros), read by the staging loads and the touched pass.
+// One thread per padded entry; grid-stride.
+__global__ void k_dist_bytes(int n, int P, const int32_t* __restrict__ A, const int32_t* __restrict__ B,
+                             int a_min, int b_min, uint8_t* Ab, uint8_t* Atb, uint8_t* Btb)
+{
+    const size_t total = (size_t)n * P;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / P), j = (int)(e - (size_t)i * P);
+        uint8_t a = 0, at = 0, bt = 0;
+        if (j < n) {
+            a = (uint8_t)(A[(size_t)i * n + j] - a_min);
+            at = (uint8_t)(A[(size_t)j * n + i] - a_min);
+            bt = (uint8_t)(B[(size_t)j * n + i] - b_min);
+        }
+        Ab[e] = a;
+        Atb[e] = at;
+        Btb[e] = bt;
+    }
+}
+
 }  // namespace
 
 int dist_quads(int n) { return (n + 3) / 4; }
 
-size_t lds_dist_bytes(int n, int G)
+size_t lds_dist_bytes(int n, int G, bool symmetric)
 {
-    return dist_layout(n, G, dist_quads(n), nullptr, nullptr);
+    return dist_layout(n, G, dist_quads(n), symmetric, nullptr, nullptr);
 }
 
-int launch_chain_dist(const DistArgs& a0, int G, int threads, hipStream_t stream)
+int launch_chain_dist(const DistArgs& a0, bool symmetric, int G, int threads, hipStream_t stream)
 {
     DistArgs a = a0;
     a.quads = dist_quads(a.n);
-    const size_t bytes = lds_dist_bytes(a.n, G);
-    const void* fn = (const void*)k_chain_dist;
+    const size_t bytes = lds_dist_bytes(a.n, G, symmetric);
+    const void* fn = symmetric ? (const void*)k_chain_dist<true> : (const void*)k_chain_dist<false>;
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
         return QAP_E_DEVICE;
     if (G > kMaxGroups || threads > 512 || a.n > kMaxPerThread * threads || (a.n + G - 1) / G > kMaxOwnRows)
         return QAP_E_INVAL;
+    if (!symmetric) {   // the byte copies precede the run on the same stream
+        if (!a.Ab || !a.Atb || !a.Btb) return QAP_E_INVAL;
+        const int P = 4 * a.quads;
+        const size_t total = (size_t)a.n * P;
+        const int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+        hipLaunchKernelGGL(k_dist_bytes, dim3(blocks), dim3(256), 0, stream, a.n, P, a.A, a.B, a.a_min, a.b_min,
+                           (uint8_t*)a.Ab, (uint8_t*)a.Atb, (uint8_t*)a.Btb);
+    }
     const int Rmax = (a.n + G - 1) / G;
     hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, stream, a.ws, a.slots, a.X, 2 * 2 * G * Rmax);
     void* kargs[] = {&a};

@@ -74,12 +74,21 @@ static_assert(sizeof(DistWs) == 64, "workspace header");
 // one 64-bit slot per workgroup, then the published Delta values (two swap
 // parities x G workgroups x ceil(n / G) own rows x {u, v}, at most
 // 2 x 2 x (n + G) ints).
+// The general (asymmetric) form adds byte copies (value - minimum, rows padded
+// to 4 * ceil(n / 4) bytes) of A, A^T and B^T, 256-byte aligned after them.
 constexpr int kMaxGroups = 1024;
-inline size_t dist_ws_bytes(int n)
+inline size_t dist_pitch(int n) { return 4 * (size_t)((n + 3) / 4); }
+inline size_t dist_ws_head(int n)
 {
-    return sizeof(DistWs) + 2 * kMaxGroups * sizeof(unsigned long long) +
-           4 * sizeof(unsigned long long) * ((size_t)n + kMaxGroups);
+    const size_t b = sizeof(DistWs) + 2 * kMaxGroups * sizeof(unsigned long long) +
+                     4 * sizeof(unsigned long long) * ((size_t)n + kMaxGroups);
+    return (b + 255) & ~(size_t)255;
 }
+inline size_t dist_ws_bytes(int n, bool sym = true)
+{
+    return dist_ws_head(n) + (sym ? 0 : 3 * (size_t)n * dist_pitch(n));
+}
+inline uint8_t* dist_bytes(void* ws, int n) { return (uint8_t*)ws + dist_ws_head(n); }
 inline unsigned long long* dist_slots(void* ws) { return (unsigned long long*)((char*)ws + sizeof(DistWs)); }
 // published Delta(r, u), Delta(r, v) of every row, two buffers by parity; each
 // entry is (tag << 32) | value, the tag naming the update that wrote it
@@ -113,6 +122,9 @@ struct DistArgs {
     DistWs* ws;
     unsigned long long* slots;   // [2][kMaxGroups]
     unsigned long long* X;
+    const uint8_t* Ab;           // general form: byte copies of A, A^T, B^T (dist_bytes)
+    const uint8_t* Atb;
+    const uint8_t* Btb;
 };
 
 // Scratch-to-Delta switch threshold (per mille of accepted proposals over
@@ -122,8 +134,8 @@ struct DistArgs {
 constexpr uint32_t kDefaultSwitchPermille = 10;
 
 int dist_quads(int n);
-size_t lds_dist_bytes(int n, int G);
-int launch_chain_dist(const DistArgs& a, int G, int threads, hipStream_t stream);
+size_t lds_dist_bytes(int n, int G, bool symmetric);
+int launch_chain_dist(const DistArgs& a, bool symmetric, int G, int threads, hipStream_t stream);
 
 // batched chains (one persistent launch, a device-wide work queue)
 struct BatchWs {

@@ -122,6 +122,9 @@ SINGLE_CHAIN_CONFIGS = {
     "n32_sym": (32, "sym_uniform", (0, 1, 2), 10**6),
     "n150_asym": (150, "asym_sparse_grid", (10, 11, 12), 10**8),
     "n2000_sym": (2000, "sym_uniform_euclid", (20, 21, 22), 10**9),
+    # the general (asymmetric) form at the same size: sparse flows on a
+    # 45-column Manhattan grid, for the multi-workgroup kernel's general update
+    "n2000_asym": (2000, "asym_sparse_grid", (23, 24, 25), 10**9),
 }
 
 _KIND = {

@@ -29,7 +29,8 @@ OUT = os.path.join(HERE, "oracle_runs.json")
 
 # (workload, t_end or None for the whole schedule, proposal order: 0 row-major, 1 random)
 SINGLE = [("n32_sym", None, 0), ("n150_asym", None, 0), ("n150_asym", 3_000_000, 0), ("n2000_sym", 2_000_000, 0),
-          ("n150_asym", None, 1), ("n2000_sym", 300_000, 1), ("n2000_sym", 20_000_000, 0)]
+          ("n150_asym", None, 1), ("n2000_sym", 300_000, 1), ("n2000_sym", 20_000_000, 0),
+          ("n2000_asym", 300_000, 0)]
 
 
 def key_of(name, t_end, order) -> str:

@@ -1,6 +1,7 @@
-"""Parity of the multi-workgroup chain kernel (symmetric instances too large
-for one CU, and smaller ones sent there by QAP_FLAG_MULTI_WG) with the CPU
-oracle, and at N=2000 against stored oracle results."""
+"""Parity of the multi-workgroup chain kernel (instances too large for one CU,
+and smaller ones sent there by QAP_FLAG_MULTI_WG), symmetric and general
+(asymmetric) forms, with the CPU oracle, and at N=2000 against stored oracle
+results."""
 import json
 import math
 import os
@@ -106,3 +107,59 @@ def test_dist_refuses_stale_delta(Q):
     c.sched.flags = Q.QAP_FLAG_MULTI_WG
     c.run(2000)
     assert c.state().status == Q.QAP_E_STATE
+
+
+def _asym(n, seed, hi=99):
+    rng = np.random.default_rng(seed)
+    A = rng.integers(0, hi + 1, (n, n)).astype(np.int32)
+    B = rng.integers(0, hi + 1, (n, n)).astype(np.int32)
+    np.fill_diagonal(A, rng.integers(0, hi + 1, n))   # the diagonal terms of Eq. (1) count too
+    return A, B, rng.permutation(n).astype(np.int32)
+
+
+@pytest.mark.parametrize("n,iters", [(9, 20000), (64, 30000), (300, 30000), (517, 20000)])
+def test_dist_general_form_matches_oracle(orc, Q, n, iters):
+    """Asymmetric A and B (non-zero diagonals): the general Taillard correction
+    (rows and columns u, v staged) and the general touched-pair recomputation."""
+    A, B, p0 = _asym(n, 900 + n)
+    _run_compare(orc, Q, A, B, p0, iters, seed=11 + n)
+
+
+def test_dist_general_form_slices_and_infinite_temperature(orc, Q):
+    A, B, p0 = _asym(280, 71)
+    _run_compare(orc, Q, A, B, p0, 30000, seed=2, slices=(1, 999, 15000, 15001))
+    got = _run_compare(orc, Q, A, B, p0, 3000, seed=1, T0=math.inf, acc_cap=3000)
+    assert got["accepts"] == 3000
+
+
+def test_dist_general_form_low_temperature(orc, Q):
+    A, B, p0 = _asym(240, 73)
+    _run_compare(orc, Q, A, B, p0, 200000, seed=3, T0=1.0)
+
+
+def test_dist_general_form_sparse_grid(orc, Q):
+    """The workload family of the asymmetric single chain (sparse flows on a
+    Manhattan grid) at a size past one CU's LDS."""
+    A, B = W.asym_sparse_grid(333, 5)
+    p0 = W.random_perm(333, 6)
+    _run_compare(orc, Q, A, B, p0, 40000, seed=4)
+
+
+def test_dist_general_form_n2000_prefix_golden(orc, Q):
+    with open(GOLD) as f:
+        g = json.load(f)["n2000_asym@300000"]
+    ch = W.single_chain("n2000_asym")
+    c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id).init()
+    assert c.sched.T0 == g["T0"] and c.sched.alpha == g["alpha"]
+    c.run(100_000)
+    c.run(300_000)
+    r = c.result(with_delta=True)
+    for k in ("accepts", "hash", "cost", "best_cost", "best_iter", "near_ties"):
+        assert r[k] == g[k], (k, r[k], g[k])
+    assert r["t"] == g["t_end"] and r["p"].tolist() == g["p"]
+    rng = np.random.default_rng(2)
+    n = ch.n
+    for _ in range(100):
+        a_, b_ = sorted(rng.choice(n, 2, replace=False))
+        idx = a_ * (2 * n - a_ - 1) // 2 + b_ - a_ - 1
+        assert r["delta"][idx] == orc.swap_cost(ch.A, ch.B, r["p"], int(a_), int(b_))

@@ -1,6 +1,7 @@
 """The largest instances the kernels take, at their real shapes: the largest
 asymmetric and symmetric chains one workgroup holds (Delta, A and B' in device
-memory), and a symmetric chain of N = 2200 on the multi-workgroup kernel.  Every
+memory), a symmetric chain of N = 2200 and an asymmetric one of N = 2000 on the
+multi-workgroup kernel.  Every
 proposal is accepted (T = +inf), so the permutation after k iterations is the
 product of the first k row-major transpositions; the cost must equal Eq. (1)
 and sampled Delta entries their definition, from the oracle."""
@@ -84,3 +85,9 @@ def test_largest_symmetric_one_workgroup(orc, Q):
 def test_symmetric_multi_workgroup_n2200(orc, Q):
     A, B = W.sym_uniform(2200, (434, 1))
     _check_forced(orc, Q, A, B, W.random_perm(2200, (435, 1)), 3000, 0)
+
+
+def test_asymmetric_multi_workgroup_n2000(orc, Q):
+    """The general (asymmetric) form at N = 2000 on the multi-workgroup kernel."""
+    ch = W.single_chain("n2000_asym")
+    _check_forced(orc, Q, ch.A, ch.B, ch.p0, 3000, 0)
