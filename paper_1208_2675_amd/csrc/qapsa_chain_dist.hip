@@ -363,8 +363,6 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     int nrec = 0;
     int tb = 0;                                    // tie buffer of the current window
     bool alive = true;
-    bool bound_ready = false;                      // bound_next holds the rejection bound of the next window
-    int32_t bound_next = 0;
 
     // Rows u, v of A and (through p) of B' after the swap (u, v): A[u][.],
     // A[v][.], B'[u][.] = B[p(v)][p(.)] and B'[v][.] = B[p(u)][p(.)], this
@@ -504,9 +502,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     while (alive && t < t_end) {
         // ------------------------------------------------------------ scan
         const uint32_t W = (uint32_t)min<uint64_t>(min<uint64_t>((uint64_t)kwin, t_end - t), (uint64_t)m);
-        // after an accepted swap the bound of this window was loaded during the update
-        const int32_t bound = bound_ready ? bound_next : reject_bound(temperature(temps, T0, t));
-        bound_ready = false;
+        const int32_t bound = reject_bound(temperature(temps, T0, t));
         unsigned long long mine = ~0ull;
         auto test = [&](uint32_t j, int d) __attribute__((always_inline)) {
             bool acc = d <= 0;
@@ -626,10 +622,6 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         // ------------------------------------------------------------ accept
         const int dstar = (int)(uint32_t)key;
         const uint64_t tstar = t + jstar;
-        // the next window starts at tstar + 1: its temperature is requested now
-        // and used after the update, so that the load's latency is hidden
-        const bool pre = tstar + 1 < t_end;
-        const double T_next = pre ? temperature(temps, T0, tstar + 1) : 0.0;
         uint32_t istar = idx0 + jstar;
         if (istar >= m) istar -= m;
         if (rnd) istar = random_pair_index(seed, chain_id, tstar, m);
@@ -859,7 +851,6 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         r0 = u; s0 = v;
         if (++s0 == n) { if (++r0 == n - 1) r0 = 0; s0 = r0 + 1; }
         kwin = a.kmin;
-        if (pre) { bound_next = reject_bound(T_next); bound_ready = true; }
         if (tid == 0) { mark(QAP_PH_DELTA_UPDATE); bump(QAP_PH_N_DELTA_ACC, 1); }
     }
 
