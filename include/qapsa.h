@@ -125,7 +125,14 @@ typedef struct {
     uint32_t switch_permille; /* a chain in scratch mode moves to Delta mode when fewer
                             than this many proposals per 1000 were accepted over the
                             last 8192 iterations; 0 selects the default (10)          */
-    uint32_t reserved;   /* must be 0                                                 */
+    uint32_t scan_window; /* the size of the subset of proposals tested at once against
+                            the unchanged Delta (Sec. 3 (ii), an adjustable parameter):
+                            multi-workgroup kernel, proposals in the first window after
+                            an accepted swap (doubling while no window accepts; 2^4 to
+                            2^21); one-workgroup kernel, the largest scan step (a
+                            multiple of 256 up to 16384, steps doubling from 256 to it);
+                            0 selects the defaults (4096 for both).  Never changes the
+                            run's result                                              */
 } qap_schedule;
 
 /* qap_schedule.flags.  The run is the same whichever mode produces the swap
@@ -245,7 +252,7 @@ QAP_API int qap_schedule_tables(uint64_t iters, double alpha, double* temps, hip
  *   iters  I, the length of the whole schedule (>= 1)
  *   final_ratio  T_{I-1} / T0, in (0, 1]; 1e-3 for the standard workloads
  *   sched  host, written: iters, t_end (= iters), T0 and alpha; seed, chain_id,
- *          flags, switch_permille and reserved are left as the caller set them
+ *          flags, switch_permille and scan_window are left as the caller set them
  * Returns QAP_E_INVAL for n < 2, iters == 0, a ratio outside (0, 1] or a null
  * pointer, info->status when it is not QAP_OK, and QAP_E_INVAL when T0 would
  * be 0 (every swap cost 0: the schedule of Eq. (2) is then undefined).

@@ -28,7 +28,8 @@ int check_schedule(const qap_schedule* s)
         return QAP_E_INVAL;
     if ((s->flags & QAP_FLAG_DELTA_ONLY) && (s->flags & QAP_FLAG_SCRATCH_ONLY)) return QAP_E_INVAL;
     if ((s->flags & QAP_FLAG_MULTI_WG) && (s->flags & QAP_FLAG_SINGLE_WG)) return QAP_E_INVAL;
-    if (s->switch_permille > 1000 || s->reserved != 0) return QAP_E_INVAL;
+    if (s->switch_permille > 1000) return QAP_E_INVAL;
+    if (s->scan_window != 0 && (s->scan_window < 16 || s->scan_window > (1u << 21))) return QAP_E_INVAL;
     return QAP_OK;
 }
 
@@ -97,7 +98,15 @@ QAP_API uint64_t qap_temp_table_len(uint64_t iters) { return temp_table_len(iter
 QAP_API uint64_t qap_workspace_bytes(int32_t n)
 {
     if (n < 2) return 0;
-    size_t bytes = dist_ws_bytes(n, false);
+    // the multi-workgroup area at the widest value type whose LDS layout fits
+    // at some grid size (at most 256 workgroups, one per CU of an MI355X)
+    size_t bytes = dist_ws_bytes(n, false, 1);
+    for (int esize = 1; esize <= 4; esize *= 2)
+        for (int sym = 0; sym < 2; ++sym)
+            if (lds_dist_bytes(n, 256, sym != 0, esize) <= kLdsLimit - kLdsStaticReserve) {
+                const size_t b = dist_ws_bytes(n, sym != 0, esize);
+                if (b > bytes) bytes = b;
+            }
     for (int sym = 0; sym < 2; ++sym) {
         const int place = wg_place(n, sym != 0);
         if (place >= 0) {
@@ -162,7 +171,9 @@ int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int3
 
     ChainArgs a{};
     a.n = n;
-    a.max_step = 16;
+    // largest Delta-mode scan step of the one-workgroup kernel, in steps of 256 proposals
+    a.max_step = sched->scan_window ? (int)((sched->scan_window + 255) / 256) : 16;
+    if (a.max_step > 64) a.max_step = 64;
     a.flags = sched->flags;
     a.switch_permille = sched->switch_permille ? sched->switch_permille : kDefaultSwitchPermille;
     a.a_min = info->a_min;
@@ -195,8 +206,22 @@ int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int3
         a.gscratch = bufs->workspace;
         return launch_chain_wg(a, sym, place, stream);
     }
-    // many workgroups, one cooperative launch: byte-valued instances
-    if (bytes_ok && !single) {
+    // value ranges wider than a byte, small enough for one CU: the 16-bit
+    // one-workgroup kernel (Delta mode only)
+    if (!bytes_ok && !multi && fits16(info->a_min, info->a_max) && fits16(info->b_min, info->b_max)) {
+        bool a_lds = false, fits = true;
+        if (lds_chain_bytes(n, sym, true) <= budget) a_lds = true;
+        else if (lds_chain_bytes(n, sym, false) > budget) fits = false;
+        if (fits) {
+            a.pitch = n | 1;
+            const int threads = n >= 64 ? 1024 : 256;
+            return launch_chain_lds(a, sym, a_lds, threads, stream);
+        }
+    }
+    // many workgroups, one cooperative launch: A and B' as bytes, 16-bit or
+    // 32-bit words by their value ranges
+    if (!single) {
+        const int esize = dist_esize((int64_t)info->a_max - info->a_min, (int64_t)info->b_max - info->b_min);
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -204,17 +229,17 @@ int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int3
         int G = (n + 7) / 8;                 // about eight rows per workgroup
         if (G > cus) G = cus;
         if (G < 2) G = 2;
-        while (G < cus && lds_dist_bytes(n, G, sym) > budget) ++G;
-        if (lds_dist_bytes(n, G, sym) <= budget) {
+        while (G < cus && lds_dist_bytes(n, G, sym, esize) > budget) ++G;
+        if (lds_dist_bytes(n, G, sym, esize) <= budget) {
             if (!bufs->workspace) return QAP_E_INVAL;
-            if (bufs->workspace_bytes < dist_ws_bytes(n, sym)) return ws_short;
+            if (bufs->workspace_bytes < dist_ws_bytes(n, sym, esize)) return ws_short;
             DistArgs d{};
             d.n = n;
             d.a_min = info->a_min;
             d.b_min = info->b_min;
             d.random_order = (sched->flags & QAP_FLAG_RANDOM_ORDER) ? 1u : 0u;
             // a random-order window is drawn whole by every workgroup: start it small
-            d.kmin = d.random_order ? 512 : 4096;
+            d.kmin = sched->scan_window ? sched->scan_window : (d.random_order ? 512 : 4096);
             d.kmax = (1u << 22) - 2;   // window offsets fit the 22-bit field of an exchange slot
             d.spin_limit = 1ull << 22;
             d.A = A; d.B = B; d.Bp = Bp; d.p = p; d.delta = delta; d.state = state;
@@ -228,16 +253,18 @@ int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int3
             d.slots = dist_slots(bufs->workspace);
             d.X = dist_X(bufs->workspace);
             if (!sym) {
-                uint8_t* bytes = dist_bytes(bufs->workspace, n);
-                const size_t plane = (size_t)n * dist_pitch(n);
-                d.Ab = bytes;
-                d.Atb = bytes + plane;
-                d.Btb = bytes + 2 * plane;
+                uint8_t* copies = dist_bytes(bufs->workspace, n);
+                const size_t plane = (size_t)n * dist_row_bytes(n, esize);
+                d.Ab = copies;
+                d.Atb = copies + plane;
+                d.Btb = copies + 2 * plane;
             }
-            return launch_chain_dist(d, sym, G, 512, stream);
+            return launch_chain_dist(d, sym, esize, G, 512, stream);
         }
-        // beyond the multi-workgroup kernel's LDS budget: one workgroup with
-        // Delta, A and B' in device memory
+    }
+    // byte-valued chains beyond the multi-workgroup kernel's LDS budget: one
+    // workgroup with Delta, A and B' in device memory
+    if (bytes_ok) {
         const int wp = wg_place(n, sym);
         if (wp >= 2) {
             if (!bufs->workspace) return QAP_E_INVAL;
@@ -246,15 +273,7 @@ int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int3
             return launch_chain_wg(a, sym, wp, stream);
         }
     }
-    // 16-bit kernel (Delta mode only)
-    if (!fits16(info->a_min, info->a_max) || !fits16(info->b_min, info->b_max)) return QAP_E_UNSUPPORTED;
-    bool a_lds;
-    if (lds_chain_bytes(n, sym, true) <= budget) a_lds = true;
-    else if (lds_chain_bytes(n, sym, false) <= budget) a_lds = false;
-    else return QAP_E_UNSUPPORTED;
-    a.pitch = n | 1;
-    const int threads = n >= 64 ? 1024 : 256;
-    return launch_chain_lds(a, sym, a_lds, threads, stream);
+    return QAP_E_UNSUPPORTED;
 }
 
 constexpr int kMaxDevices = 64;

@@ -1,5 +1,6 @@
 // qapsa_chain_dist.hip -- one annealing chain spread over G workgroups, for
-// symmetric instances too large for one CU (N up to about 3000 on 256 CUs).
+// instances too large for one CU (N up to about 2600 symmetric and 2000
+// asymmetric on 256 CUs with byte-range values, less with wider values).
 //
 // Steps (b)-(e) of Sec. 2.2 with the Delta matrix kept for every pair.  The
 // state is split by rows: workgroup w owns rows r = w, w + G, w + 2G, ... of
@@ -51,6 +52,30 @@ __device__ __forceinline__ unsigned long long uni64(unsigned long long x)
 }
 __device__ __forceinline__ uint32_t dot4(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_udot4(a, b, c, false); }
 
+// Element types of A and B' (value minus the matrix minimum): bytes when both
+// value ranges fit 0..255, 16-bit words up to 65535, else 32-bit words.  Every
+// swap cost is a combination of products of such values that the Delta bound
+// keeps inside int32, so all sums are taken modulo 2^32 (wrapping dot products
+// and multiplies) and come out exact.
+template <typename E> struct Elem;
+template <> struct Elem<uint8_t> {
+    static constexpr uint32_t kMax = 0xffu;
+    // four products of a word's bytes, added to c modulo 2^32
+    static __device__ __forceinline__ uint32_t dot(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_udot4(a, b, c, false); }
+};
+template <> struct Elem<uint16_t> {
+    static constexpr uint32_t kMax = 0xffffu;
+    static __device__ __forceinline__ uint32_t dot(uint32_t a, uint32_t b, uint32_t c)
+    {
+        typedef unsigned short v2u16 __attribute__((ext_vector_type(2)));
+        return __builtin_amdgcn_udot2(__builtin_bit_cast(v2u16, a), __builtin_bit_cast(v2u16, b), c, false);
+    }
+};
+template <> struct Elem<uint32_t> {
+    static constexpr uint32_t kMax = 0xffffffffu;
+    static __device__ __forceinline__ uint32_t dot(uint32_t a, uint32_t b, uint32_t c) { return a * b + c; }
+};
+
 __device__ __forceinline__ int wave_sum(int v)
 {
     v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
@@ -88,22 +113,25 @@ __device__ __forceinline__ void pair_of_u(int n, uint32_t idx, int& r, int& s)
 // form): the k = r and k = s terms are dropped and the two terms of Eq. (1)
 // with both indices in {r, s} are added.  Arguments are shifted entries at
 // (r,r), (r,s), (s,r), (s,s) of A and B'.
-__device__ __forceinline__ int finish_gen(int S, int arr, int ars, int asr, int ass, int brr, int brs, int bsr, int bss)
+// (Arithmetic modulo 2^32: exact for every value width, see Elem.)
+__device__ __forceinline__ int finish_gen(uint32_t S, uint32_t arr, uint32_t ars, uint32_t asr, uint32_t ass,
+                                          uint32_t brr, uint32_t brs, uint32_t bsr, uint32_t bss)
 {
-    const int corner = (arr - ass) * (bss - brr) + (ars - asr) * (bsr - brs);
-    const int row_r = (arr - asr) * (bsr - brr);
-    const int row_s = (ars - ass) * (bss - brs);
-    const int col_r = (arr - ars) * (brs - brr);
-    const int col_s = (asr - ass) * (bss - bsr);
-    return S - row_r - row_s - col_r - col_s + corner;
+    const uint32_t corner = (arr - ass) * (bss - brr) + (ars - asr) * (bsr - brs);
+    const uint32_t row_r = (arr - asr) * (bsr - brr);
+    const uint32_t row_s = (ars - ass) * (bss - brs);
+    const uint32_t col_r = (arr - ars) * (brs - brr);
+    const uint32_t col_s = (asr - ass) * (bss - bsr);
+    return (int)(S - row_r - row_s - col_r - col_s + corner);
 }
 
-__device__ __forceinline__ int finish_sym(int S, int arr, int ars, int asr, int ass, int brr, int brs, int bsr, int bss)
+__device__ __forceinline__ int finish_sym(uint32_t S, uint32_t arr, uint32_t ars, uint32_t asr, uint32_t ass,
+                                          uint32_t brr, uint32_t brs, uint32_t bsr, uint32_t bss)
 {
-    const int corner = (arr - ass) * (bss - brr) + (ars - asr) * (bsr - brs);
-    const int row_r = (arr - asr) * (bsr - brr);
-    const int row_s = (ars - ass) * (bss - brs);
-    return 2 * (S - row_r - row_s) + corner;
+    const uint32_t corner = (arr - ass) * (bss - brr) + (ars - asr) * (bsr - brs);
+    const uint32_t row_r = (arr - asr) * (bsr - brr);
+    const uint32_t row_s = (ars - ass) * (bss - brs);
+    return (int)(2u * (S - row_r - row_s) + corner);
 }
 
 // Wait until this wave's global stores have completed (vmcnt = 0).
@@ -120,21 +148,24 @@ __device__ __forceinline__ void raise_err(int* p, int code)
     __hip_atomic_fetch_max(p, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Rows are P elements (4 q bytes, zero padded); see Elem for the element types.
 struct Lds {
     int32_t* D;      // [R][n] full rows of Delta
-    uint8_t* Ab;     // [R][P] rows of A - a_min (symmetric form; the general form reads A from device memory)
-    uint8_t* Bb;     // [R][P] rows of B' - b_min
-    uint8_t* Bt;     // [R][P] columns of B' - b_min (general form)
-    uint8_t* Su;     // [P] row u of A - a_min
-    uint8_t* Sv;
-    uint8_t* Tu;     // [P] row u of B' - b_min after the swap
-    uint8_t* Tv;
-    uint8_t* Scu;    // [P] column u of A - a_min (general form)
-    uint8_t* Scv;
-    uint8_t* Tcu;    // [P] column u of B' - b_min after the swap (general form)
-    uint8_t* Tcv;
-    uint32_t* abp;   // [n] int16 pair: (A[k][u]-A[k][v], A[u][k]-A[v][k]), equal halves when symmetric
-    uint32_t* bbp;   // [n] int16 pair: (B'[k][u]-B'[k][v], B'[u][k]-B'[v][k]) after the swap
+    char* Ab;        // [R][P] rows of A - a_min (symmetric form; the general form reads A from device memory)
+    char* Bb;        // [R][P] rows of B' - b_min
+    char* Bt;        // [R][P] columns of B' - b_min (general form)
+    char* Su;        // [P] row u of A - a_min
+    char* Sv;
+    char* Tu;        // [P] row u of B' - b_min after the swap
+    char* Tv;
+    char* Scu;       // [P] column u of A - a_min (general form)
+    char* Scv;
+    char* Tcu;       // [P] column u of B' - b_min after the swap (general form)
+    char* Tcv;
+    // per k: (A[k][u]-A[k][v], A[u][k]-A[v][k]) and (B'[k][u]-B'[k][v], B'[u][k]-B'[v][k])
+    // after the swap (equal halves when symmetric): int16 pairs for bytes, int32 pairs otherwise
+    char* abp;
+    char* bbp;
     int16_t* ps;     // [n]
 };
 
@@ -144,9 +175,10 @@ __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15;
 // columns of B' beside its rows and stages columns u, v as well as rows; its
 // rows and columns of A are read from byte copies in device memory instead
 // (they never change), so that N = 2000 still fits one CU's LDS.
-__host__ __device__ inline size_t dist_layout(int n, int G, int q, bool sym, char* base, Lds* L)
+__host__ __device__ inline size_t dist_layout(int n, int G, int q, int esize, bool sym, char* base, Lds* L)
 {
-    const size_t R = (size_t)(n + G - 1) / G, P = 4 * (size_t)q;
+    const size_t R = (size_t)(n + G - 1) / G, P = 4 * (size_t)q;   // P: row bytes here
+    const size_t pw = esize == 1 ? 4 : 8;                          // bytes of one difference pair
     size_t off = 0;
     auto take = [&](size_t b) { char* p = base ? base + off : nullptr; off = a16(off + b); return p; };
     char* d = take(4 * R * n);
@@ -161,14 +193,14 @@ __host__ __device__ inline size_t dist_layout(int n, int G, int q, bool sym, cha
     char* scv = sym ? nullptr : take(P);
     char* tcu = sym ? nullptr : take(P);
     char* tcv = sym ? nullptr : take(P);
-    char* abp = take(4 * (size_t)n);
-    char* bbp = take(4 * (size_t)n);
+    char* abp = take(pw * (size_t)n);
+    char* bbp = take(pw * (size_t)n);
     char* ps = take(2 * (size_t)n);
     if (L) {
-        L->D = (int32_t*)d; L->Ab = (uint8_t*)ab; L->Bb = (uint8_t*)bb; L->Bt = (uint8_t*)bt;
-        L->Su = (uint8_t*)su; L->Sv = (uint8_t*)sv; L->Tu = (uint8_t*)tu; L->Tv = (uint8_t*)tv;
-        L->Scu = (uint8_t*)scu; L->Scv = (uint8_t*)scv; L->Tcu = (uint8_t*)tcu; L->Tcv = (uint8_t*)tcv;
-        L->abp = (uint32_t*)abp; L->bbp = (uint32_t*)bbp; L->ps = (int16_t*)ps;
+        L->D = (int32_t*)d; L->Ab = ab; L->Bb = bb; L->Bt = bt;
+        L->Su = su; L->Sv = sv; L->Tu = tu; L->Tv = tv;
+        L->Scu = scu; L->Scv = scv; L->Tcu = tcu; L->Tcv = tcv;
+        L->abp = abp; L->bbp = bbp; L->ps = (int16_t*)ps;
     }
     return off;
 }
@@ -232,9 +264,11 @@ __device__ __noinline__ bool exact_test(int d, const double* temps, double T0, u
     return metropolis_positive(d, temperature(temps, T0, t), uniform_r(seed, chain, t), z);
 }
 
-template <bool SYM>
+template <bool SYM, typename E>
 __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
 {
+    constexpr bool kByte = sizeof(E) == 1;
+    constexpr int kEpw = 4 / (int)sizeof(E);   // elements per 32-bit word
     extern __shared__ __align__(16) char smem[];
     __shared__ unsigned long long s_wkey[16];    // first acceptance per wave of the window
     __shared__ unsigned long long s_key;         // the grid-wide first acceptance
@@ -251,31 +285,33 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
 
     const int n = a.n, G = gridDim.x, w = blockIdx.x;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = uni(tid >> 6), nwaves = nt >> 6;
-    const int q = a.quads, P = 4 * q;
+    const int q = a.quads, P = kEpw * q;      // words and elements per row
     const int Rw = (n - w + G - 1) / G;          // rows owned by this workgroup
     const int C = Rw;                             // columns s = w + G c of this workgroup (same count)
     const uint32_t m = (uint32_t)((int64_t)n * (n - 1) / 2);
     Lds L_;
-    dist_layout(n, G, q, SYM, smem, &L_);
+    dist_layout(n, G, q, (int)sizeof(E), SYM, smem, &L_);
     // the LDS arrays as plain pointer values
     int32_t* const lD = L_.D;
-    uint8_t* const lAb = L_.Ab;
-    uint8_t* const lBb = L_.Bb;
-    uint8_t* const lBt = L_.Bt;
-    uint8_t* const lSu = L_.Su;
-    uint8_t* const lSv = L_.Sv;
-    uint8_t* const lTu = L_.Tu;
-    uint8_t* const lTv = L_.Tv;
-    uint8_t* const lScu = L_.Scu;
-    uint8_t* const lScv = L_.Scv;
-    uint8_t* const lTcu = L_.Tcu;
-    uint8_t* const lTcv = L_.Tcv;
-    // general form: byte copies (value - minimum, rows padded to P) in device memory
-    const uint8_t* __restrict__ const gA = a.Ab;     // A
-    const uint8_t* __restrict__ const gAt = a.Atb;   // A^T
-    const uint8_t* __restrict__ const gBt = a.Btb;   // B^T
-    uint32_t* const labp = L_.abp;
-    uint32_t* const lbbp = L_.bbp;
+    E* const lAb = (E*)L_.Ab;
+    E* const lBb = (E*)L_.Bb;
+    E* const lBt = (E*)L_.Bt;
+    E* const lSu = (E*)L_.Su;
+    E* const lSv = (E*)L_.Sv;
+    E* const lTu = (E*)L_.Tu;
+    E* const lTv = (E*)L_.Tv;
+    E* const lScu = (E*)L_.Scu;
+    E* const lScv = (E*)L_.Scv;
+    E* const lTcu = (E*)L_.Tcu;
+    E* const lTcv = (E*)L_.Tcv;
+    uint32_t* const labp = (uint32_t*)L_.abp;   // bytes: int16 pairs
+    uint32_t* const lbbp = (uint32_t*)L_.bbp;
+    uint2* const labp2 = (uint2*)L_.abp;        // wider values: int32 pairs
+    uint2* const lbbp2 = (uint2*)L_.bbp;
+    // general form: copies (value - minimum, rows padded to P) in device memory
+    const E* __restrict__ const gA = (const E*)a.Ab;     // A
+    const E* __restrict__ const gAt = (const E*)a.Atb;   // A^T
+    const E* __restrict__ const gBt = (const E*)a.Btb;   // B^T
     int16_t* const lps = L_.ps;
     DistWs* ws = a.ws;
     // published values, workgroup-major: [2 parities][G workgroups][Rmax own rows][2]
@@ -308,16 +344,16 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             lD[lr * n + s] = d;
         }
         for (int k = tid; k < P; k += nt) {
-            int av = 0, bv = 0, cv = 0;
+            uint32_t av = 0, bv = 0, cv = 0;
             if (k < n) {
-                av = a.A[r * n + k] - a.a_min;
-                bv = a.Bp[r * n + k] - a.b_min;
-                if (!SYM) cv = a.Bp[k * n + r] - a.b_min;   // column r of B'
-                if ((av | bv | cv) & ~0xff) s_ok = 0;
+                av = (uint32_t)a.A[r * n + k] - (uint32_t)a.a_min;
+                bv = (uint32_t)a.Bp[r * n + k] - (uint32_t)a.b_min;
+                if (!SYM) cv = (uint32_t)a.Bp[k * n + r] - (uint32_t)a.b_min;   // column r of B'
+                if (av > Elem<E>::kMax || bv > Elem<E>::kMax || cv > Elem<E>::kMax) s_ok = 0;
             }
-            if constexpr (SYM) lAb[lr * P + k] = (uint8_t)av;
-            lBb[lr * P + k] = (uint8_t)bv;
-            if constexpr (!SYM) lBt[lr * P + k] = (uint8_t)cv;
+            if constexpr (SYM) lAb[lr * P + k] = (E)av;
+            lBb[lr * P + k] = (E)bv;
+            if constexpr (!SYM) lBt[lr * P + k] = (E)cv;
         }
     }
     for (int k = tid; k < P; k += nt) {
@@ -368,8 +404,10 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     // A[v][.], B'[u][.] = B[p(v)][p(.)] and B'[v][.] = B[p(u)][p(.)], this
     // thread's columns, all loads issued before any result is used.
     const int nk = (n + nt - 1) / nt;   // columns per thread (uniform)
-    // The general form also stages columns u, v of A and of B': their shifted
-    // bytes, packed four to a register (A[k][u], A[k][v], B'[k][u], B'[k][v]).
+    // The general form also stages columns u, v of A and of B' (A[k][u],
+    // A[k][v], B'[k][u], B'[k][v] from the copies of A^T and B^T): bytes packed
+    // four to a register in ge here; wider values are read where they are
+    // written to LDS (four more registers per column would spill).
     auto stage_loads = [&](int u, int v, int* ga, int* gb, int* gc, int* gd, uint32_t* ge)
         __attribute__((always_inline)) {
         const int pu_new = uni((int)lps[v]), pv_new = uni((int)lps[u]);
@@ -382,7 +420,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             gb[i] = a.A[v * n + k];
             gc[i] = a.B[pu_new * n + pk];
             gd[i] = a.B[pv_new * n + pk];
-            if constexpr (!SYM) {
+            if constexpr (!SYM && kByte) {
                 ge[i] = (uint32_t)gAt[(size_t)u * P + k] | ((uint32_t)gAt[(size_t)v * P + k] << 8) |
                         ((uint32_t)gBt[(size_t)pu_new * P + pk] << 16) | ((uint32_t)gBt[(size_t)pv_new * P + pk] << 24);
             }
@@ -647,53 +685,67 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         if (!(spec && jstar == 0)) stage_loads(u, v, ga, gb, gc, gd, ge);
         // staged bytes, packed differences and this thread's share of the self
         // terms <A[x][.], B'[x][.]> of x = u, v
-        int self_u = 0, self_v = 0;
+        uint32_t self_u = 0, self_v = 0;   // modulo 2^32 (see Elem)
 #pragma unroll
         for (int i = 0; i < kMaxPerThread; ++i) {
             if (i >= nk) break;
             const int k = tid + i * nt;
             if (k < n) {
-                const int su = ga[i] - a.a_min, sv = gb[i] - a.a_min, tu = gc[i] - a.b_min, tv = gd[i] - a.b_min;
-                lSu[k] = (uint8_t)su;
-                lSv[k] = (uint8_t)sv;
-                lTu[k] = (uint8_t)tu;
-                lTv[k] = (uint8_t)tv;
-                const int da = su - sv, db = tu - tv;
+                const uint32_t su = (uint32_t)ga[i] - (uint32_t)a.a_min, sv = (uint32_t)gb[i] - (uint32_t)a.a_min;
+                const uint32_t tu = (uint32_t)gc[i] - (uint32_t)a.b_min, tv = (uint32_t)gd[i] - (uint32_t)a.b_min;
+                lSu[k] = (E)su;
+                lSv[k] = (E)sv;
+                lTu[k] = (E)tu;
+                lTv[k] = (E)tv;
+                const uint32_t da = su - sv, db = tu - tv;
+                uint32_t dc = da, dt = db;   // column differences (the row ones when symmetric)
                 if constexpr (SYM) {
-                    labp[k] = (uint32_t)(uint16_t)da | ((uint32_t)(uint16_t)da << 16);
-                    lbbp[k] = (uint32_t)(uint16_t)db | ((uint32_t)(uint16_t)db << 16);
                     self_u += su * tu;
                     self_v += sv * tv;
                 } else {
-                    const int cu = ge[i] & 0xff, cv = (ge[i] >> 8) & 0xff;
-                    const int tcu = (ge[i] >> 16) & 0xff, tcv = ge[i] >> 24;
-                    lScu[k] = (uint8_t)cu;
-                    lScv[k] = (uint8_t)cv;
-                    lTcu[k] = (uint8_t)tcu;
-                    lTcv[k] = (uint8_t)tcv;
-                    const int dc = cu - cv, dt = tcu - tcv;
-                    labp[k] = (uint32_t)(uint16_t)dc | ((uint32_t)(uint16_t)da << 16);
-                    lbbp[k] = (uint32_t)(uint16_t)dt | ((uint32_t)(uint16_t)db << 16);
+                    uint32_t cu, cv, tcu, tcv;
+                    if constexpr (kByte) {
+                        cu = ge[i] & 0xff; cv = (ge[i] >> 8) & 0xff; tcu = (ge[i] >> 16) & 0xff; tcv = ge[i] >> 24;
+                    } else {
+                        const int pk = k == u ? pu_new : (k == v ? pv_new : (int)lps[k]);
+                        cu = gAt[(size_t)u * P + k];
+                        cv = gAt[(size_t)v * P + k];
+                        tcu = gBt[(size_t)pu_new * P + pk];
+                        tcv = gBt[(size_t)pv_new * P + pk];
+                    }
+                    lScu[k] = (E)cu;
+                    lScv[k] = (E)cv;
+                    lTcu[k] = (E)tcu;
+                    lTcv[k] = (E)tcv;
+                    dc = cu - cv;
+                    dt = tcu - tcv;
                     self_u += su * tu + cu * tcu;
                     self_v += sv * tv + cv * tcv;
                 }
+                if constexpr (kByte) {
+                    labp[k] = (uint32_t)(uint16_t)dc | ((uint32_t)(uint16_t)da << 16);
+                    lbbp[k] = (uint32_t)(uint16_t)dt | ((uint32_t)(uint16_t)db << 16);
+                } else {
+                    labp2[k] = make_uint2(dc, da);
+                    lbbp2[k] = make_uint2(dt, db);
+                }
             }
         }
-        self_u = wave_sum(self_u);
-        self_v = wave_sum(self_v);
-        if (lane == 0) { s_selfw[wave][0] = self_u; s_selfw[wave][1] = self_v; }
+        self_u = (uint32_t)wave_sum((int)self_u);
+        self_v = (uint32_t)wave_sum((int)self_v);
+        if (lane == 0) { s_selfw[wave][0] = (int)self_u; s_selfw[wave][1] = (int)self_v; }
         // own rows of B' other than u, v swap columns u, v (thread lr for own
         // row lr); nothing reads B' between the exchange and the touched pass
         for (int lr = tid; lr < Rw; lr += nt) {
             const int r = w + G * lr;
             if (r != u && r != v) {
-                uint8_t* row = lBb + lr * P;
-                const uint8_t x = row[u];
+                E* row = lBb + lr * P;
+                const E x = row[u];
                 row[u] = row[v];
                 row[v] = x;
                 if constexpr (!SYM) {   // column r of B': its entries u, v change places too
-                    uint8_t* col = lBt + lr * P;
-                    const uint8_t y = col[u];
+                    E* col = lBt + lr * P;
+                    const E y = col[u];
                     col[u] = col[v];
                     col[v] = y;
                 }
@@ -706,12 +758,12 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         for (int which = 0; which < 2; ++which) {
             const int x = which == 0 ? u : v;
             if (x % G != w) continue;
-            uint8_t* row = lBb + (x / G) * P;
-            const uint8_t* src = which == 0 ? lTu : lTv;
+            E* row = lBb + (x / G) * P;
+            const E* src = which == 0 ? lTu : lTv;
             for (int k = tid; k < n; k += nt) row[k] = src[k];
             if constexpr (!SYM) {
-                uint8_t* col = lBt + (x / G) * P;
-                const uint8_t* srcc = which == 0 ? lTcu : lTcv;
+                E* col = lBt + (x / G) * P;
+                const E* srcc = which == 0 ? lTcu : lTcv;
                 for (int k = tid; k < n; k += nt) col[k] = srcc[k];
             }
         }
@@ -733,6 +785,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         // read.  So the only mask is the end of the row.
         {
             constexpr int kRowBatch = 8;
+            if constexpr (kByte) {
             for (int lr0 = 0; lr0 < Rw; lr0 += kRowBatch) {
                 v2i16 ar[kRowBatch], br[kRowBatch];
 #pragma unroll
@@ -771,33 +824,63 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                     }
                 }
             }
+            } else {
+            // wider values: the two products in 32-bit arithmetic modulo 2^32
+            for (int lr0 = 0; lr0 < Rw; lr0 += kRowBatch) {
+                uint2 ar[kRowBatch], br[kRowBatch];
+#pragma unroll
+                for (int h = 0; h < kRowBatch; ++h) {
+                    const int lr = lr0 + h < Rw ? lr0 + h : Rw - 1;
+                    const int r = w + G * lr;
+                    ar[h] = labp2[r];
+                    br[h] = lbbp2[r];
+                }
+                for (int i = 0; i < nk; ++i) {
+                    const int s = tid + i * nt;
+                    if (s >= n) continue;
+                    const uint2 as = labp2[s], bs = lbbp2[s];
+                    uint32_t dv[kRowBatch];
+#pragma unroll
+                    for (int h = 0; h < kRowBatch; ++h) {
+                        const int lr = lr0 + h < Rw ? lr0 + h : Rw - 1;
+                        dv[h] = (uint32_t)lD[lr * n + s];
+                    }
+#pragma unroll
+                    for (int h = 0; h < kRowBatch; ++h)
+                        if (lr0 + h < Rw)
+                            lD[(lr0 + h) * n + s] = (int32_t)(dv[h] + (ar[h].x - as.x) * (bs.x - br[h].x) +
+                                                              (ar[h].y - as.y) * (bs.y - br[h].y));
+                }
+            }
+            }
         }
         // Delta(r, u), Delta(r, v) of own rows: one wave per row
         {
-            int su = 0, sv = 0;
-        for (int i = 0; i < nwaves; ++i) { su += s_selfw[i][0]; sv += s_selfw[i][1]; }
-        su = uni(su);
-        sv = uni(sv);
+            uint32_t su = 0, sv = 0;
+            for (int i = 0; i < nwaves; ++i) { su += (uint32_t)s_selfw[i][0]; sv += (uint32_t)s_selfw[i][1]; }
+            su = uni(su);
+            sv = uni(sv);
             for (int lr = wave; lr < Rw; lr += nwaves) {
                 const int r = w + G * lr;
                 if (r == u || r == v) continue;
                 // own row r of A: LDS (symmetric form) or the byte copy in device memory
-                const uint8_t* A_r = SYM ? lAb + lr * P : gA + (size_t)r * P;
+                const E* A_r = SYM ? lAb + lr * P : gA + (size_t)r * P;
                 const uint32_t* ar = (const uint32_t*)A_r;
                 const uint32_t* br = (const uint32_t*)(lBb + lr * P);
-                const uint8_t* B_r = lBb + lr * P;
-                const int arr = A_r[r], aru = A_r[u], arv = A_r[v], brr = B_r[r], bru = B_r[u], brv = B_r[v];
-                const int sur = lSu[r], suu = lSu[u], svr = lSv[r], svv = lSv[v];
-                const int tur = lTu[r], tuu = lTu[u], tvr = lTv[r], tvv = lTv[v];
+                const E* B_r = lBb + lr * P;
+                const uint32_t arr = A_r[r], aru = A_r[u], arv = A_r[v], brr = B_r[r], bru = B_r[u], brv = B_r[v];
+                const uint32_t sur = lSu[r], suu = lSu[u], svr = lSv[r], svv = lSv[v];
+                const uint32_t tur = lTu[r], tuu = lTu[u], tvr = lTv[r], tvv = lTv[v];
+                auto dot = [](uint32_t x, uint32_t y, uint32_t c) { return Elem<E>::dot(x, y, c); };
                 uint32_t pu_ = 0, pv_ = 0, self = 0;
                 if constexpr (SYM) {
                     for (int k = lane; k < q; k += 64) {
                         const uint32_t xa = ar[k], xb = br[k];
-                        pu_ = dot4(xa, ((const uint32_t*)lTu)[k], pu_);
-                        pu_ = dot4(((const uint32_t*)lSu)[k], xb, pu_);
-                        pv_ = dot4(xa, ((const uint32_t*)lTv)[k], pv_);
-                        pv_ = dot4(((const uint32_t*)lSv)[k], xb, pv_);
-                        self = dot4(xa, xb, self);
+                        pu_ = dot(xa, ((const uint32_t*)lTu)[k], pu_);
+                        pu_ = dot(((const uint32_t*)lSu)[k], xb, pu_);
+                        pv_ = dot(xa, ((const uint32_t*)lTv)[k], pv_);
+                        pv_ = dot(((const uint32_t*)lSv)[k], xb, pv_);
+                        self = dot(xa, xb, self);
                     }
                 } else {
                     // rows and columns: column r of A from the copy of A^T, column r of B' in LDS
@@ -805,19 +888,20 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                     const uint32_t* dr = (const uint32_t*)(lBt + lr * P);
                     for (int k = lane; k < q; k += 64) {
                         const uint32_t xa = ar[k], xb = br[k], xc = cr[k], xd = dr[k];
-                        pu_ = dot4(xa, ((const uint32_t*)lTu)[k], pu_);
-                        pu_ = dot4(((const uint32_t*)lSu)[k], xb, pu_);
-                        pu_ = dot4(xc, ((const uint32_t*)lTcu)[k], pu_);
-                        pu_ = dot4(((const uint32_t*)lScu)[k], xd, pu_);
-                        pv_ = dot4(xa, ((const uint32_t*)lTv)[k], pv_);
-                        pv_ = dot4(((const uint32_t*)lSv)[k], xb, pv_);
-                        pv_ = dot4(xc, ((const uint32_t*)lTcv)[k], pv_);
-                        pv_ = dot4(((const uint32_t*)lScv)[k], xd, pv_);
-                        self = dot4(xa, xb, self);
-                        self = dot4(xc, xd, self);
+                        pu_ = dot(xa, ((const uint32_t*)lTu)[k], pu_);
+                        pu_ = dot(((const uint32_t*)lSu)[k], xb, pu_);
+                        pu_ = dot(xc, ((const uint32_t*)lTcu)[k], pu_);
+                        pu_ = dot(((const uint32_t*)lScu)[k], xd, pu_);
+                        pv_ = dot(xa, ((const uint32_t*)lTv)[k], pv_);
+                        pv_ = dot(((const uint32_t*)lSv)[k], xb, pv_);
+                        pv_ = dot(xc, ((const uint32_t*)lTcv)[k], pv_);
+                        pv_ = dot(((const uint32_t*)lScv)[k], xd, pv_);
+                        self = dot(xa, xb, self);
+                        self = dot(xc, xd, self);
                     }
                 }
-                const int Pu = wave_sum((int)pu_), Pv = wave_sum((int)pv_), Sr = wave_sum((int)self);
+                const uint32_t Pu = (uint32_t)wave_sum((int)pu_), Pv = (uint32_t)wave_sum((int)pv_);
+                const uint32_t Sr = (uint32_t)wave_sum((int)self);
                 if (lane == 0) {
                     if constexpr (SYM) {
                         s_pub[2 * lr] = finish_sym(Pu - Sr - su, arr, aru, sur, suu, brr, bru, tur, tuu);
@@ -865,7 +949,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         const int r = w + G * lr;
         int32_t* up = a.delta + rs32(n, r) - r - 1;
         for (int s = r + 1 + tid; s < n; s += nt) up[s] = lD[lr * n + s];
-        for (int k = tid; k < n; k += nt) a.Bp[r * n + k] = (int32_t)lBb[lr * P + k] + a.b_min;
+        for (int k = tid; k < n; k += nt) a.Bp[r * n + k] = (int32_t)((uint32_t)lBb[lr * P + k] + (uint32_t)a.b_min);
     }
     if (w == 0) {
         for (int i = tid; i < n; i += nt) a.p[i] = lps[i];
@@ -902,20 +986,21 @@ __global__ void k_ws_reset(DistWs* ws, unsigned long long* slots, unsigned long 
     }
 }
 
-// General form: byte copies (value - minimum) of A, A^T and B^T with rows
-// padded to P bytes (zeros), read by the staging loads and the touched pass.
-// One thread per padded entry; grid-stride.
-__global__ void k_dist_bytes(int n, int P, const int32_t* __restrict__ A, const int32_t* __restrict__ B,
-                             int a_min, int b_min, uint8_t* Ab, uint8_t* Atb, uint8_t* Btb)
+// General form: copies (value - minimum, element type E) of A, A^T and B^T
+// with rows padded to P elements (zeros), read by the staging loads and the
+// touched pass.  One thread per padded entry; grid-stride.
+template <typename E>
+__global__ void k_dist_copies(int n, int P, const int32_t* __restrict__ A, const int32_t* __restrict__ B,
+                              int a_min, int b_min, E* Ab, E* Atb, E* Btb)
 {
     const size_t total = (size_t)n * P;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(e / P), j = (int)(e - (size_t)i * P);
-        uint8_t a = 0, at = 0, bt = 0;
+        E a = 0, at = 0, bt = 0;
         if (j < n) {
-            a = (uint8_t)(A[(size_t)i * n + j] - a_min);
-            at = (uint8_t)(A[(size_t)j * n + i] - a_min);
-            bt = (uint8_t)(B[(size_t)j * n + i] - b_min);
+            a = (E)((uint32_t)A[(size_t)i * n + j] - (uint32_t)a_min);
+            at = (E)((uint32_t)A[(size_t)j * n + i] - (uint32_t)a_min);
+            bt = (E)((uint32_t)B[(size_t)j * n + i] - (uint32_t)b_min);
         }
         Ab[e] = a;
         Atb[e] = at;
@@ -923,32 +1008,19 @@ __global__ void k_dist_bytes(int n, int P, const int32_t* __restrict__ A, const 
     }
 }
 
-}  // namespace
-
-int dist_quads(int n) { return (n + 3) / 4; }
-
-size_t lds_dist_bytes(int n, int G, bool symmetric)
+template <typename E>
+int launch_dist_typed(DistArgs& a, bool symmetric, int G, int threads, size_t bytes, hipStream_t stream)
 {
-    return dist_layout(n, G, dist_quads(n), symmetric, nullptr, nullptr);
-}
-
-int launch_chain_dist(const DistArgs& a0, bool symmetric, int G, int threads, hipStream_t stream)
-{
-    DistArgs a = a0;
-    a.quads = dist_quads(a.n);
-    const size_t bytes = lds_dist_bytes(a.n, G, symmetric);
-    const void* fn = symmetric ? (const void*)k_chain_dist<true> : (const void*)k_chain_dist<false>;
+    const void* fn = symmetric ? (const void*)k_chain_dist<true, E> : (const void*)k_chain_dist<false, E>;
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
         return QAP_E_DEVICE;
-    if (G > kMaxGroups || threads > 512 || a.n > kMaxPerThread * threads || (a.n + G - 1) / G > kMaxOwnRows)
-        return QAP_E_INVAL;
-    if (!symmetric) {   // the byte copies precede the run on the same stream
+    if (!symmetric) {   // the copies precede the run on the same stream
         if (!a.Ab || !a.Atb || !a.Btb) return QAP_E_INVAL;
-        const int P = 4 * a.quads;
+        const int P = a.quads * (4 / (int)sizeof(E));
         const size_t total = (size_t)a.n * P;
         const int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
-        hipLaunchKernelGGL(k_dist_bytes, dim3(blocks), dim3(256), 0, stream, a.n, P, a.A, a.B, a.a_min, a.b_min,
-                           (uint8_t*)a.Ab, (uint8_t*)a.Atb, (uint8_t*)a.Btb);
+        hipLaunchKernelGGL(k_dist_copies<E>, dim3(blocks), dim3(256), 0, stream, a.n, P, a.A, a.B, a.a_min, a.b_min,
+                           (E*)a.Ab, (E*)a.Atb, (E*)a.Btb);
     }
     const int Rmax = (a.n + G - 1) / G;
     hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, stream, a.ws, a.slots, a.X, 2 * 2 * G * Rmax);
@@ -956,6 +1028,30 @@ int launch_chain_dist(const DistArgs& a0, bool symmetric, int G, int threads, hi
     if (hipLaunchCooperativeKernel(fn, dim3(G), dim3(threads), kargs, (unsigned)bytes, stream) != hipSuccess)
         return QAP_E_DEVICE;
     return QAP_OK;
+}
+
+}  // namespace
+
+int dist_words(int n, int esize) { return (int)(((size_t)n * esize + 3) / 4); }
+
+size_t lds_dist_bytes(int n, int G, bool symmetric, int esize)
+{
+    return dist_layout(n, G, dist_words(n, esize), esize, symmetric, nullptr, nullptr);
+}
+
+int launch_chain_dist(const DistArgs& a0, bool symmetric, int esize, int G, int threads, hipStream_t stream)
+{
+    DistArgs a = a0;
+    a.quads = dist_words(a.n, esize);
+    const size_t bytes = lds_dist_bytes(a.n, G, symmetric, esize);
+    if (G > kMaxGroups || threads > 512 || a.n > kMaxPerThread * threads || (a.n + G - 1) / G > kMaxOwnRows)
+        return QAP_E_INVAL;
+    switch (esize) {
+    case 1: return launch_dist_typed<uint8_t>(a, symmetric, G, threads, bytes, stream);
+    case 2: return launch_dist_typed<uint16_t>(a, symmetric, G, threads, bytes, stream);
+    case 4: return launch_dist_typed<uint32_t>(a, symmetric, G, threads, bytes, stream);
+    default: return QAP_E_INVAL;
+    }
 }
 
 }  // namespace qapsa

@@ -74,19 +74,20 @@ static_assert(sizeof(DistWs) == 64, "workspace header");
 // one 64-bit slot per workgroup, then the published Delta values (two swap
 // parities x G workgroups x ceil(n / G) own rows x {u, v}, at most
 // 2 x 2 x (n + G) ints).
-// The general (asymmetric) form adds byte copies (value - minimum, rows padded
-// to 4 * ceil(n / 4) bytes) of A, A^T and B^T, 256-byte aligned after them.
+// The general (asymmetric) form adds copies (value - minimum, elements of
+// esize bytes, rows padded to a multiple of 4 bytes) of A, A^T and B^T,
+// 256-byte aligned after them.
 constexpr int kMaxGroups = 1024;
-inline size_t dist_pitch(int n) { return 4 * (size_t)((n + 3) / 4); }
+inline size_t dist_row_bytes(int n, int esize) { return 4 * (((size_t)n * esize + 3) / 4); }
 inline size_t dist_ws_head(int n)
 {
     const size_t b = sizeof(DistWs) + 2 * kMaxGroups * sizeof(unsigned long long) +
                      4 * sizeof(unsigned long long) * ((size_t)n + kMaxGroups);
     return (b + 255) & ~(size_t)255;
 }
-inline size_t dist_ws_bytes(int n, bool sym = true)
+inline size_t dist_ws_bytes(int n, bool sym, int esize)
 {
-    return dist_ws_head(n) + (sym ? 0 : 3 * (size_t)n * dist_pitch(n));
+    return dist_ws_head(n) + (sym ? 0 : 3 * (size_t)n * dist_row_bytes(n, esize));
 }
 inline uint8_t* dist_bytes(void* ws, int n) { return (uint8_t*)ws + dist_ws_head(n); }
 inline unsigned long long* dist_slots(void* ws) { return (unsigned long long*)((char*)ws + sizeof(DistWs)); }
@@ -96,7 +97,7 @@ inline unsigned long long* dist_X(void* ws) { return dist_slots(ws) + 2 * kMaxGr
 
 struct DistArgs {
     int32_t n;
-    int32_t quads;
+    int32_t quads;               // 32-bit words per row of A and B' (set at launch)
     int32_t a_min, b_min;
     uint32_t kmin, kmax;         // scan window bounds (proposals)
     uint32_t random_order;       // 1: pairs drawn per iteration (QAP_FLAG_RANDOM_ORDER)
@@ -122,9 +123,9 @@ struct DistArgs {
     DistWs* ws;
     unsigned long long* slots;   // [2][kMaxGroups]
     unsigned long long* X;
-    const uint8_t* Ab;           // general form: byte copies of A, A^T, B^T (dist_bytes)
-    const uint8_t* Atb;
-    const uint8_t* Btb;
+    const void* Ab;              // general form: copies of A, A^T, B^T (dist_bytes)
+    const void* Atb;
+    const void* Btb;
 };
 
 // Scratch-to-Delta switch threshold (per mille of accepted proposals over
@@ -133,9 +134,16 @@ struct DistArgs {
 // 1.3% slower, 160 60% slower).  The threshold never changes a run's result.
 constexpr uint32_t kDefaultSwitchPermille = 10;
 
-int dist_quads(int n);
-size_t lds_dist_bytes(int n, int G, bool symmetric);
-int launch_chain_dist(const DistArgs& a, bool symmetric, int G, int threads, hipStream_t stream);
+// element size of the multi-workgroup kernel for value ranges a_range, b_range:
+// 1 (both <= 255), 2 (<= 65535) or 4
+inline int dist_esize(int64_t a_range, int64_t b_range)
+{
+    const int64_t r = a_range > b_range ? a_range : b_range;
+    return r <= 255 ? 1 : (r <= 65535 ? 2 : 4);
+}
+int dist_words(int n, int esize);
+size_t lds_dist_bytes(int n, int G, bool symmetric, int esize);
+int launch_chain_dist(const DistArgs& a, bool symmetric, int esize, int G, int threads, hipStream_t stream);
 
 // batched chains (one persistent launch, a device-wide work queue)
 struct BatchWs {

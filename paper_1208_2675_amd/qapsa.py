@@ -51,7 +51,7 @@ class NearTie(C.Structure):
 class Schedule(C.Structure):
     _fields_ = [("iters", C.c_uint64), ("t_end", C.c_uint64), ("T0", C.c_double), ("alpha", C.c_double),
                 ("seed", C.c_uint64), ("chain_id", C.c_uint32), ("flags", C.c_uint32),
-                ("switch_permille", C.c_uint32), ("reserved", C.c_uint32)]
+                ("switch_permille", C.c_uint32), ("scan_window", C.c_uint32)]
 
 
 class TabuSchedule(C.Structure):
@@ -220,7 +220,8 @@ class Chain:
 
     def __init__(self, A, B, p0, iters: int, seed: int, chain_id: int = 0, ratio: float = 1e-3,
                  T0: float | None = None, device: str = "cuda", stream=None, tie_cap: int = 64,
-                 accept_cap: int = 0, flags: int = 0, switch_permille: int = 0, profile: bool = False):
+                 accept_cap: int = 0, flags: int = 0, switch_permille: int = 0, profile: bool = False,
+                 scan_window: int = 0):
         import torch
         self.torch = torch
         A = np.ascontiguousarray(A, dtype=np.int32)
@@ -229,7 +230,7 @@ class Chain:
         self.m = n * (n - 1) // 2
         self.iters = int(iters)
         self.seed, self.chain_id, self.ratio, self.T0_override = int(seed), int(chain_id), ratio, T0
-        self.flags, self.switch_permille = int(flags), int(switch_permille)
+        self.flags, self.switch_permille, self.scan_window = int(flags), int(switch_permille), int(scan_window)
         self.stream = stream
         dev = torch.device(device)
         self.A = torch.from_numpy(A).to(dev)
@@ -263,6 +264,7 @@ class Chain:
         self.sched.chain_id = self.chain_id
         self.sched.flags = self.flags
         self.sched.switch_permille = self.switch_permille
+        self.sched.scan_window = self.scan_window
         _check(qap_schedule_tables(self.iters, self.sched.alpha, self.temps, self.stream), "qap_schedule_tables")
         return self
 

@@ -64,9 +64,9 @@ def test_host_side_argument_errors(qlib):
     assert Q.qap_temp_table_len(10**9) == 2048 + 954
     assert Q.qap_temp_table_len(1) == 2049
     q = lambda n: (((n + 3) // 4) | 1) * 4
-    for n in (2, 150):   # everything in LDS: the multi-workgroup area (asymmetric form) is the larger
+    for n in (2, 150):   # everything in LDS: the multi-workgroup area (asymmetric, 32-bit values) is the larger
         head = (64 + 2 * 1024 * 8 + 32 * (n + 1024) + 255) // 256 * 256
-        assert Q.qap_workspace_bytes(n) == head + 3 * n * 4 * ((n + 3) // 4)
+        assert Q.qap_workspace_bytes(n) == head + 3 * n * 4 * n
     # n = 2000: A, A^T, B', B'^T as bytes in device scratch (asymmetric chain)
     assert Q.qap_workspace_bytes(2000) == 4 * 2000 * q(2000)
     assert Q.qap_single_workgroup(150, 0, 99, 23) == 1 and Q.qap_single_workgroup(195, 1, 99, 99) == 1
@@ -97,7 +97,8 @@ def test_host_side_argument_errors(qlib):
     assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, fake, ok, bad_info, bufs, 0) == Q.QAP_E_RANGE
     # values outside the 16-bit working range have no single-workgroup kernel
     wide = Q.InstanceInfo(0, 0, 0, 70000, 0, 9, 1, 0)
-    assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, fake, ok, wide, bufs, 0) == Q.QAP_E_UNSUPPORTED
+    single = Q.Schedule(100, 100, 1.0, 0.5, 1, 0, Q.QAP_FLAG_SINGLE_WG, 0, 0)
+    assert Q.qap_sa_run(8, fake, fake, fake, fake, fake, fake, single, wide, bufs, 0) == Q.QAP_E_UNSUPPORTED
     # batches run four waves per chain: other workgroup sizes are refused
     one = (Q.ChainDesc * 1)()
     assert Q.qap_sa_run_batch(1, one, fake, None, Q.BatchConfig(128, 0, 0, None), fake, 0) == Q.QAP_E_INVAL

@@ -163,3 +163,24 @@ def test_dist_general_form_n2000_prefix_golden(orc, Q):
         a_, b_ = sorted(rng.choice(n, 2, replace=False))
         idx = a_ * (2 * n - a_ - 1) // 2 + b_ - a_ - 1
         assert r["delta"][idx] == orc.swap_cost(ch.A, ch.B, r["p"], int(a_), int(b_))
+
+
+@pytest.mark.parametrize("sym", [True, False])
+@pytest.mark.parametrize("flags,window", [(16, 0), (16, 256), (16, 16384), (4, 16), (4, 1024), (4, 65536)])
+def test_dispatch_choices_do_not_change_the_run(orc, Q, sym, flags, window):
+    """Every (kernel, scan window) the dispatch tuner may pick gives the
+    oracle's run: QAP_FLAG_SINGLE_WG (16) or QAP_FLAG_MULTI_WG (4), windows
+    from 16 proposals to 65536."""
+    n, iters = 230, 40000
+    A, B, p0 = _sym(n, 77) if sym else _asym(n, 78)
+    s = orc.schedule(A, B, p0, iters)
+    ref = orc.sa_run(A, B, p0, iters, s["T0"], s["alpha"], 6, 0, tie_cap=16)
+    print(f"[case] dispatch n={n} sym={sym} flags={flags} window={window}", flush=True)
+    c = Q.Chain(A, B, p0, iters, 6, 0, flags=flags, scan_window=window).init()
+    c.run(15000)
+    c.run()
+    got = c.result(with_delta=True)
+    for k in ("t", "accepts", "hash", "cost", "best_cost", "best_iter", "near_ties"):
+        assert got[k] == ref[k], (k, got[k], ref[k])
+    assert np.array_equal(got["p"], ref["p"])
+    assert np.array_equal(got["delta"], orc.delta_matrix(A, B, got["p"]))

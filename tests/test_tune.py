@@ -23,3 +23,18 @@ def test_representatives_have_the_bucket_shape():
     assert (ch.A.diagonal() == 0).all()
     ch = tune._representative(20, 60, True, 10)
     assert ch.n == 40 and (ch.A == ch.A.T).all() and (ch.B == ch.B.T).all()
+
+
+def test_dispatch_for_takes_the_nearest_measured_size():
+    table = {"iters": 1, "entries": [
+        {"n": 200, "symmetric": True, "flags": tune.FLAG_SINGLE_WG, "scan_window": 1024},
+        {"n": 700, "symmetric": True, "flags": tune.FLAG_MULTI_WG, "scan_window": 4096},
+        {"n": 300, "symmetric": False, "flags": tune.FLAG_MULTI_WG, "scan_window": 16384},
+    ]}
+    assert tune.dispatch_for(table, 200, True) == (tune.FLAG_SINGLE_WG, 1024)
+    assert tune.dispatch_for(table, 449, True) == (tune.FLAG_SINGLE_WG, 1024)
+    assert tune.dispatch_for(table, 451, True) == (tune.FLAG_MULTI_WG, 4096)
+    assert tune.dispatch_for(table, 5000, True) == (tune.FLAG_MULTI_WG, 4096)
+    assert tune.dispatch_for(table, 120, True) == (0, 0)       # one workgroup's LDS: the library decides
+    assert tune.dispatch_for(table, 2000, False) == (tune.FLAG_MULTI_WG, 16384)
+    assert tune.dispatch_for(None, 2000, False) == (0, 0)
