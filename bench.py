@@ -155,6 +155,34 @@ def cpu_baseline_many(chains, prefix: int, what: str) -> dict:
                       f"on the acceptance rate, so a prefix measures its rate"}
 
 
+def _comparator_chain(ch):
+    import cpu_comparator
+    import oracle
+    s = oracle.schedule(ch.A, ch.B, ch.p0, ch.iters)
+    cpu_comparator.sa_run(ch.A, ch.B, ch.p0, ch.iters, s["T0"], s["alpha"], ch.philox_seed, ch.chain_id)
+    return ch.iters
+
+
+def cpu_comparator_many(chains, what: str) -> dict:
+    """The paper's comparator type on all host threads: one CPU Delta-matrix
+    chain per thread at a time, each over its whole schedule (its cost per
+    iteration changes along the schedule, so a prefix would not measure it);
+    aggregate iterations/s over the wall time of the sample."""
+    import cpu_comparator
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    cpu_comparator.build()
+    oracle.build()
+    k = cpu_threads()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(k) as ex:
+        total = sum(ex.map(_comparator_chain, chains))
+    dt = time.perf_counter() - t0
+    return {"value": total / dt, "unit": "iterations/s", "cores": k, "kind": "delta_matrix_comparator",
+            "sample": f"{what}: {len(chains)} chains, whole schedules (T0 from the oracle's Delta_0, inside "
+                      f"the timing), one chain per thread on {k} threads ({dt:.1f} s)"}
+
+
 class CpuJobs:
     """CPU baselines run one after another on a background thread (each one
     single- or multi-threaded as it states), so that they overlap the untimed
@@ -355,6 +383,8 @@ def section_batched(Q, W, torch, args, jobs=None):
     out["ratio_vs_single_chain"] = out["value"] / single_rate
     if jobs and "batched_cpu" in jobs:
         out["cpu_baseline"] = jobs["batched_cpu"]
+    if jobs and "batched_cpu_comparator" in jobs:
+        out["cpu_baseline_comparator"] = jobs["batched_cpu_comparator"]
     return out
 
 
@@ -475,6 +505,8 @@ def section_serve(Q, W, torch, args, jobs=None):
                            "with the request's position in the trace"}
     if jobs and "serve_cpu" in jobs:
         out["cpu_baseline"] = jobs["serve_cpu"]
+    if jobs and "serve_cpu_comparator" in jobs:
+        out["cpu_baseline_comparator"] = jobs["serve_cpu_comparator"]
     return out
 
 
@@ -591,11 +623,17 @@ def make_cpu_jobs(W, args, sections) -> CpuJobs:
         sample = mix[:: max(1, len(mix) // 64)][:64]   # one chain per instance
         jobs.add("batched_cpu", lambda: cpu_baseline_many(sample, args.cpu_prefix_batched,
                                                           "one chain of each of the mix's 64 instances"))
+        if not args.no_comparator:
+            jobs.add("batched_cpu_comparator", lambda: cpu_comparator_many(
+                sample, "one chain of each of the mix's 64 instances"))
     if "serve" in sections:
         reqs = W.served_trace(n_requests=args.serve_requests, iters=args.serve_iters)
         sample = [q.chain for q in reqs[:: max(1, len(reqs) // 64)][:64]]
         jobs.add("serve_cpu", lambda: cpu_baseline_many(sample, args.cpu_prefix_serve,
                                                         "every k-th request of the served trace"))
+        if not args.no_comparator:
+            jobs.add("serve_cpu_comparator", lambda: cpu_comparator_many(
+                sample, "every k-th request of the served trace"))
     return jobs
 
 

@@ -131,8 +131,9 @@ typedef struct {
                             an accepted swap (doubling while no window accepts; 2^4 to
                             2^21); one-workgroup kernel, the largest scan step (a
                             multiple of 256 up to 16384, steps doubling from 256 to it);
-                            0 selects the defaults (4096 for both).  Never changes the
-                            run's result                                              */
+                            0 selects the defaults (256, and 512 in random order, on the
+                            grid; 4096 on one workgroup).  Never changes the run's
+                            result                                                    */
 } qap_schedule;
 
 /* qap_schedule.flags.  The run is the same whichever mode produces the swap

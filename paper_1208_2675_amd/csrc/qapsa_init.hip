@@ -120,12 +120,11 @@ __global__ void k_zero64(int64_t* x) { *x = 0; }
 // columns r and s of A and B' (rows k) and rows r and s (columns k).
 constexpr int kTile = 32;
 
-__global__ void __launch_bounds__(256) k_delta_init(int n, const int32_t* __restrict__ A,
-                                                    const int32_t* __restrict__ Bp,
-                                                    int32_t* __restrict__ delta,
-                                                    qap_instance_info* info)
+// Body of the Delta build for one tile; returns this thread's sum of |Delta|
+// and sets *overflow when an entry does not fit int32.
+__device__ __forceinline__ long long delta_tile(int n, const int32_t* __restrict__ A, const int32_t* __restrict__ Bp,
+                                                int32_t* __restrict__ delta, int* overflow_out)
 {
-    if (info->status != QAP_OK) return;
     // tiles (tr, ts) with ts >= tr, enumerated in row-major order of the tile triangle
     const int nt = (n + kTile - 1) / kTile;
     int tr = 0;
@@ -197,6 +196,19 @@ __global__ void __launch_bounds__(256) k_delta_init(int n, const int32_t* __rest
             local_abs += d < 0 ? -d : d;
         }
     }
+    *overflow_out = overflow;
+    return local_abs;
+}
+
+__global__ void __launch_bounds__(256) k_delta_init(int n, const int32_t* __restrict__ A,
+                                                    const int32_t* __restrict__ Bp,
+                                                    int32_t* __restrict__ delta,
+                                                    qap_instance_info* info)
+{
+    if (info->status != QAP_OK) return;
+    int overflow = 0;
+    long long local_abs = delta_tile(n, A, Bp, delta, &overflow);
+    const int tid = threadIdx.x;
     for (int off = 32; off > 0; off >>= 1) {
         local_abs += __shfl_xor(local_abs, off);
         overflow |= __shfl_xor(overflow, off);
@@ -205,6 +217,30 @@ __global__ void __launch_bounds__(256) k_delta_init(int n, const int32_t* __rest
         atomicAdd((unsigned long long*)&info->sum_abs_delta, (unsigned long long)local_abs);
         if (overflow) atomicCAS(&info->status, (int)QAP_OK, (int)QAP_E_RANGE);
     }
+}
+
+// A chain that stopped in scratch mode (Delta left stale) either to move to
+// Delta mode before t_end or at the end of its schedule gets its Delta matrix
+// rebuilt for the current p from B' (kept current by every run); any other
+// chain is left alone.  The condition is read from the device state, so a
+// caller can queue the rebuild without knowing whether it is needed.
+__device__ __forceinline__ bool needs_rebuild(const qap_chain_state* st, uint64_t t_end, uint64_t iters)
+{
+    return st->status == QAP_OK && st->mode == QAP_MODE_SCRATCH_STALE && (st->t < t_end || st->t >= iters);
+}
+
+__global__ void __launch_bounds__(256) k_delta_rebuild(int n, const int32_t* __restrict__ A,
+                                                       const int32_t* __restrict__ Bp, int32_t* __restrict__ delta,
+                                                       const qap_chain_state* st, uint64_t t_end, uint64_t iters)
+{
+    if (!needs_rebuild(st, t_end, iters)) return;
+    int overflow = 0;
+    (void)delta_tile(n, A, Bp, delta, &overflow);   // the instance passed the bound check: no overflow
+}
+
+__global__ void k_rebuild_done(qap_chain_state* st, uint64_t t_end, uint64_t iters)
+{
+    if (needs_rebuild(st, t_end, iters)) st->mode = st->t >= iters ? QAP_MODE_SCRATCH : QAP_MODE_DELTA;
 }
 
 __global__ void k_state_reset(const qap_instance_info* info, qap_chain_state* st)
@@ -280,6 +316,17 @@ int launch_delta_init(int n, const int32_t* A, const int32_t* B, const int32_t* 
     const int tiles = nt * (nt + 1) / 2;
     hipLaunchKernelGGL(k_delta_init, dim3(tiles), dim3(256), 0, stream, n, A, Bp, delta, info);
     if (state) hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, stream, info, state);
+    return hipGetLastError() == hipSuccess ? QAP_OK : QAP_E_DEVICE;
+}
+
+int launch_delta_rebuild(int n, const int32_t* A, const int32_t* Bp, int32_t* delta, qap_chain_state* state,
+                         uint64_t t_end, uint64_t iters, hipStream_t stream)
+{
+    clear_error();
+    const int nt = (n + kTile - 1) / kTile;
+    const int tiles = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(k_delta_rebuild, dim3(tiles), dim3(256), 0, stream, n, A, Bp, delta, state, t_end, iters);
+    hipLaunchKernelGGL(k_rebuild_done, dim3(1), dim3(1), 0, stream, state, t_end, iters);
     return hipGetLastError() == hipSuccess ? QAP_OK : QAP_E_DEVICE;
 }
 

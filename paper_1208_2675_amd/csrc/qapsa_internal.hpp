@@ -59,6 +59,11 @@ int launch_delta_init(int n, const int32_t* A, const int32_t* B, const int32_t* 
                       int32_t* delta, qap_instance_info* info, qap_chain_state* state,
                       hipStream_t stream);
 int launch_schedule_tables(uint64_t iters, double alpha, double* temps, hipStream_t stream);
+// Delta for the current p of a chain whose state says it stopped in scratch
+// mode before t_end or at the end of its schedule (read on the device; a no-op
+// otherwise), then the mode: QAP_MODE_DELTA, or QAP_MODE_SCRATCH at t = iters.
+int launch_delta_rebuild(int n, const int32_t* A, const int32_t* Bp, int32_t* delta, qap_chain_state* state,
+                         uint64_t t_end, uint64_t iters, hipStream_t stream);
 int launch_chain_lds(const ChainArgs& a, bool symmetric, bool a_in_lds, int threads,
                      hipStream_t stream);
 
