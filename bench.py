@@ -411,7 +411,10 @@ def section_update(Q, W, torch, args):
     log(f"update: n={n} forced accepts={per * launches} in {launches} launches")
     # one untimed launch of the same size first (first-launch set-up of the
     # cooperative kernel), then the timed ones
-    c = Q.Chain(ch.A, ch.B, ch.p0, per * (launches + 1), ch.philox_seed, ch.chain_id, T0=math.inf)
+    # Delta mode throughout: the update of Sec. 3 is what is timed (scratch mode
+    # would otherwise run the whole forced-accept schedule)
+    c = Q.Chain(ch.A, ch.B, ch.p0, per * (launches + 1), ch.philox_seed, ch.chain_id, T0=math.inf,
+                flags=Q.QAP_FLAG_DELTA_ONLY)
     c.init()
     c.run(per)
     torch.cuda.synchronize()
@@ -434,7 +437,8 @@ def section_update(Q, W, torch, args):
            "bytes_per_launch": bytes_per * per, "achieved_GBs": achieved, "accepts": int(st.accepts),
            "status": int(st.status), "parity": parity}
     if args.phases:   # one more launch of the same size with the phase clock of workgroup 0 (untimed)
-        cp = Q.Chain(ch.A, ch.B, ch.p0, per, ch.philox_seed, ch.chain_id, T0=math.inf, profile=True).init()
+        cp = Q.Chain(ch.A, ch.B, ch.p0, per, ch.philox_seed, ch.chain_id, T0=math.inf, profile=True,
+                     flags=Q.QAP_FLAG_DELTA_ONLY).init()
         cp.run(per)
         ph = cp.phases()
         out["phase_cycles_per_update"] = {k: round(ph[k] / per, 1) for k in

@@ -124,7 +124,8 @@ typedef struct {
     uint32_t flags;      /* 0 or QAP_FLAG_* below                                      */
     uint32_t switch_permille; /* a chain in scratch mode moves to Delta mode when fewer
                             than this many proposals per 1000 were accepted over the
-                            last 8192 iterations; 0 selects the default (10)          */
+                            last 8192 iterations; 0 selects the default (10 on one
+                            workgroup, 20 over many workgroups)                        */
     uint32_t scan_window; /* the size of the subset of proposals tested at once against
                             the unchanged Delta (Sec. 3 (ii), an adjustable parameter):
                             multi-workgroup kernel, proposals in the first window after
@@ -223,7 +224,8 @@ QAP_API int qap_delta_init(int32_t n, const int32_t* A, const int32_t* B, const 
 
 /* Bytes of device workspace a run of an n-facility instance may need
    (qap_run_buffers.workspace): the larger of the multi-workgroup area (the
-   exchange slots and published values, 49216 + 32 n rounded up to 256, plus
+   exchange slots, published values and scratch-mode partial sums, 311360 + 32 n
+   rounded up to 256, plus
    for asymmetric instances byte copies of A, A^T and B^T, 3 n * 4 ceil(n/4))
    and the one-workgroup scratch for asymmetric chains (qap_chain_scratch_bytes(n, 0)). */
 QAP_API uint64_t qap_workspace_bytes(int32_t n);
@@ -280,9 +282,13 @@ QAP_API int qap_schedule_init(int32_t n, const qap_instance_info* info, uint64_t
  * proposal's swap cost is computed in O(n) when it is met; Delta is rebuilt
  * when the chain moves to Delta mode and when a call ends the schedule
  * (t = iters), and is otherwise left stale (state->mode says which).  The
- * multi-workgroup and 16-bit kernels need a current Delta and fail with
- * QAP_E_STATE on a stale one.  The run is identical whatever the split of
- * [0, iters) into calls and whichever mode is active.
+ * 16-bit kernel needs a current Delta and fails with QAP_E_STATE on a stale
+ * one.  The multi-workgroup kernel runs both modes: in scratch mode every
+ * workgroup sums its own rows' terms of the swap costs of a window of up to 16
+ * proposals and the workgroups exchange these partial sums; when the chain
+ * moves to Delta mode the call rebuilds Delta between two launches and goes
+ * on.  The run is identical whatever the split of [0, iters) into calls and
+ * whichever mode is active.
  * Kernels: one workgroup holds the chain when its B' fits one CU's LDS
  * (Delta and then A moving to device memory first); otherwise (symmetric
  * instances up to about 2600 facilities, asymmetric ones up to about 2000)

@@ -255,6 +255,9 @@ int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int3
             d.ws = (DistWs*)bufs->workspace;
             d.slots = dist_slots(bufs->workspace);
             d.X = dist_X(bufs->workspace);
+            d.Pp = dist_P(bufs->workspace, n);
+            d.flags = sched->flags & (QAP_FLAG_DELTA_ONLY | QAP_FLAG_SCRATCH_ONLY);
+            d.switch_permille = sched->switch_permille ? sched->switch_permille : kDefaultDistSwitchPermille;
             if (!sym) {
                 uint8_t* copies = dist_bytes(bufs->workspace, n);
                 const size_t plane = (size_t)n * dist_row_bytes(n, esize);

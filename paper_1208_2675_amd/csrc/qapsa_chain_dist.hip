@@ -264,7 +264,10 @@ __device__ __noinline__ bool exact_test(int d, const double* temps, double T0, u
     return metropolis_positive(d, temperature(temps, T0, t), uniform_r(seed, chain, t), z);
 }
 
-template <bool SYM, typename E>
+// SCR: the scratch-mode instantiation (returns at once when the chain is to
+// run in Delta mode); otherwise the Delta-mode one.  Two instantiations keep
+// the registers of each mode to themselves.
+template <bool SYM, typename E, bool SCR>
 __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
 {
     constexpr bool kByte = sizeof(E) == 1;
@@ -282,11 +285,14 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     __shared__ double s_tie_z[2][kTieSlots];
     __shared__ Rec s_rec[kRec];
     __shared__ unsigned long long s_prof[QAP_PHASES];
+    __shared__ uint32_t s_gsum[16][kScratchK];   // scratch mode: per-wave sums of the gathered partials
+    __shared__ int s_swap[4];                     // scratch mode: u, v and their new p values
 
     const int n = a.n, G = gridDim.x, w = blockIdx.x;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = uni(tid >> 6), nwaves = nt >> 6;
     const int q = a.quads, P = kEpw * q;      // words and elements per row
     const int Rw = (n - w + G - 1) / G;          // rows owned by this workgroup
+    const int Rmax = (n + G - 1) / G;
     const int C = Rw;                             // columns s = w + G c of this workgroup (same count)
     const uint32_t m = (uint32_t)((int64_t)n * (n - 1) / 2);
     Lds L_;
@@ -316,7 +322,6 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     DistWs* ws = a.ws;
     // published values, workgroup-major: [2 parities][G workgroups][Rmax own rows][2]
     unsigned long long* X = a.X;
-    const int Rmax = (n + G - 1) / G;
 
     const bool prof = a.prof != nullptr && w == 0;
     if (tid < QAP_PHASES) s_prof[tid] = 0;
@@ -332,28 +337,44 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     auto bump = [&](int k, unsigned long long x) __attribute__((always_inline)) { if (prof && tid == 0) atomicAdd(&s_prof[k], x); };
 
     // ---------------------------------------------------------------- load
+    // A call with nothing to do (failed chain, or t already at t_end) leaves
+    // everything as it is.  Scratch mode (forced, or the chain's state says
+    // Delta is not being kept and Delta mode is not forced) needs no Delta: the LDS of the
+    // Delta rows holds the general form's own rows and columns of A instead,
+    // when they fit there.
+    const qap_chain_state st0 = *a.state;
+    if (st0.status != QAP_OK || st0.t >= a.t_end) return;
+    const bool scr = SCR && ((a.flags & kFlagDeltaOnly) ? false : (a.flags & kFlagScratchOnly) ? true
+                                                                                             : st0.mode != QAP_MODE_DELTA);
+    if (SCR && !scr) return;
+    const bool a_lds = !SYM && scr && 2 * (size_t)P * sizeof(E) <= 4 * (size_t)n;
+    E* const lAr = (E*)lD;                        // [R][P] own rows of A - a_min (general form, scratch mode)
+    E* const lAc = lAr + (size_t)Rmax * P;        // [R][P] own columns of A - a_min
     if (tid == 0) { s_ok = 1; s_rf_bad = 0; s_ntie[0] = 0; s_ntie[1] = 0; }
     __syncthreads();
     for (int lr = 0; lr < Rw; ++lr) {
         const int r = w + G * lr;
         const int32_t* up = a.delta + rs32(n, r) - r - 1;   // row r, s > r
-        for (int s = tid; s < n; s += nt) {
-            int d = 0;
-            if (s > r) d = up[s];
-            else if (s < r) d = a.delta[rs32(n, s) + r - s - 1];
-            lD[lr * n + s] = d;
-        }
+        if (!scr)
+            for (int s = tid; s < n; s += nt) {
+                int d = 0;
+                if (s > r) d = up[s];
+                else if (s < r) d = a.delta[rs32(n, s) + r - s - 1];
+                lD[lr * n + s] = d;
+            }
         for (int k = tid; k < P; k += nt) {
-            uint32_t av = 0, bv = 0, cv = 0;
+            uint32_t av = 0, bv = 0, cv = 0, ac = 0;
             if (k < n) {
                 av = (uint32_t)a.A[r * n + k] - (uint32_t)a.a_min;
                 bv = (uint32_t)a.Bp[r * n + k] - (uint32_t)a.b_min;
                 if (!SYM) cv = (uint32_t)a.Bp[k * n + r] - (uint32_t)a.b_min;   // column r of B'
-                if (av > Elem<E>::kMax || bv > Elem<E>::kMax || cv > Elem<E>::kMax) s_ok = 0;
+                if (a_lds) ac = (uint32_t)a.A[k * n + r] - (uint32_t)a.a_min;   // column r of A
+                if (av > Elem<E>::kMax || bv > Elem<E>::kMax || cv > Elem<E>::kMax || ac > Elem<E>::kMax) s_ok = 0;
             }
             if constexpr (SYM) lAb[lr * P + k] = (E)av;
             lBb[lr * P + k] = (E)bv;
             if constexpr (!SYM) lBt[lr * P + k] = (E)cv;
+            if (a_lds) { lAr[lr * P + k] = (E)av; lAc[lr * P + k] = (E)ac; }
         }
     }
     for (int k = tid; k < P; k += nt) {
@@ -365,12 +386,9 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         if (pi < 0 || pi >= n) s_ok = 0;   // p indexes B below
         lps[i] = (int16_t)pi;
     }
-    const qap_chain_state st0 = *a.state;
     __syncthreads();
-    if (!s_ok || st0.status != QAP_OK || st0.mode == QAP_MODE_SCRATCH_STALE) {
-        if (w == 0 && tid == 0)
-            a.state->status = st0.status != QAP_OK ? st0.status
-                              : st0.mode == QAP_MODE_SCRATCH_STALE ? QAP_E_STATE : QAP_E_INVAL;
+    if (!s_ok || (!scr && st0.mode == QAP_MODE_SCRATCH_STALE)) {
+        if (w == 0 && tid == 0) a.state->status = s_ok ? QAP_E_STATE : QAP_E_INVAL;
         return;   // every workgroup takes the same branch: the instance and state are shared
     }
     if (tid == 0) mark(QAP_PH_IO);
@@ -536,6 +554,241 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         }
         nrec = 0;
     };
+
+    // ---------------------------------------------------------------- scratch mode
+    // Each proposal's swap cost is computed when it is met (Sec. 2.2 (c)),
+    // split over the workgroups by rows: a window of K proposals is taken in
+    // order, every workgroup sums the terms k of its own rows (k not in
+    // {r, s}) for each of them and publishes K tagged partial sums, and every
+    // workgroup adds up all partials and the two terms with both indices in
+    // {r, s}, so that all of them take the same decisions.  The first accepted
+    // proposal of the window is made and the window restarts after it.  A swap
+    // (u, v) changes p, columns u, v of every row of B' (local), and rows u, v
+    // of B' (read again through p by their owners).  Delta is not kept: the
+    // run leaves it stale, and returns as soon as the acceptance rate over
+    // the last 8192 or more iterations falls below switch_permille per 1000,
+    // for Delta to be rebuilt and the run continued in Delta mode.
+    if constexpr (SCR) {
+        uint32_t K = 4;                           // proposals per window: 4, 8 or 16
+        uint64_t win_iters = 0, win_acc = 0;
+        const uint32_t flags = a.flags, switch_permille = a.switch_permille;
+        unsigned long long* const Pbase = a.Pp;
+        while (alive && t < t_end) {
+            const uint32_t W = (uint32_t)min<uint64_t>(min<uint64_t>((uint64_t)K, t_end - t), (uint64_t)m);
+            epoch += 1;
+            const uint32_t tag = (uint32_t)epoch;
+            unsigned long long* const Pw = Pbase + (size_t)(epoch & 1) * kMaxGroups * kScratchK;
+            // wave 0: this workgroup's partial sums, one proposal per lane j < K
+            // (lanes j, j + K, ... split the own rows), and the loads of the
+            // entries of A and B that enter through both indices
+            const int j = lane & (int)(K - 1);
+            int r = 0, s = 1;
+            int32_t arr = 0, ass = 0, ars = 0, asr = 0, brr = 0, bss = 0, brs = 0, bsr = 0;
+            if (wave == 0) {
+                uint32_t idx = idx0 + (uint32_t)j;
+                if (idx >= m) idx -= m;
+                if (rnd) idx = random_pair_index(seed, chain_id, t + (uint64_t)j, m);
+                pair_of_u(n, idx, r, s);
+                uint32_t part = 0;   // modulo 2^32 (see Elem)
+                if ((uint32_t)j < W) {
+                    for (int lr = lane / (int)K; lr < Rw; lr += 64 / (int)K) {
+                        const int k = w + G * lr;
+                        if (k == r || k == s) continue;
+                        const E* Bk = lBb + lr * P;   // row k of B'
+                        if constexpr (SYM) {
+                            const E* Ak = lAb + lr * P;
+                            part += ((uint32_t)Ak[r] - (uint32_t)Ak[s]) * ((uint32_t)Bk[s] - (uint32_t)Bk[r]);
+                        } else {
+                            // row k of A, column k of A (Ck[x] = A[x][k]) and column k of B' (Dk[x] = B'[x][k])
+                            const E* Ak = a_lds ? lAr + lr * P : gA + (size_t)k * P;
+                            const E* Ck = a_lds ? lAc + lr * P : gAt + (size_t)k * P;
+                            const E* Dk = lBt + lr * P;
+                            part += ((uint32_t)Ak[r] - (uint32_t)Ak[s]) * ((uint32_t)Bk[s] - (uint32_t)Bk[r]);
+                            part += ((uint32_t)Ck[r] - (uint32_t)Ck[s]) * ((uint32_t)Dk[s] - (uint32_t)Dk[r]);
+                        }
+                    }
+                }
+                for (int off = (int)K; off < 64; off <<= 1) part += (uint32_t)__shfl_xor((int)part, off);
+                if (lane < (int)K) put64(Pw + w * K + lane, ((unsigned long long)tag << 32) | part);
+                if (lane < (int)K && (uint32_t)j < W) {
+                    const int pr = lps[r], ps = lps[s];
+                    arr = a.A[r * n + r]; ass = a.A[s * n + s]; ars = a.A[r * n + s]; asr = a.A[s * n + r];
+                    brr = a.B[pr * n + pr]; bss = a.B[ps * n + ps]; brs = a.B[pr * n + ps]; bsr = a.B[ps * n + pr];
+                }
+            }
+            if (tid == 0) mark(QAP_PH_SCRATCH_EVAL);
+            // every workgroup's partials of this window (thread tid takes
+            // proposal tid mod K: the block size is a multiple of K)
+            {
+                const int total = G * (int)K;
+                uint32_t acc = 0;
+                bool bad = false;
+                for (int e0 = tid; e0 < total && !bad; e0 += 8 * nt) {
+                    unsigned long long x[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int e = e0 + i * nt;
+                        x[i] = e < total ? get64(Pw + e) : ((unsigned long long)tag << 32);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int e = e0 + i * nt;
+                        uint64_t spins = 0;
+                        while (!bad && (uint32_t)(x[i] >> 32) != tag) {
+                            if (++spins > spin_limit || ((spins & 63) == 0 && get(&ws->err))) { bad = true; break; }
+                            __builtin_amdgcn_s_sleep(1);
+                            x[i] = get64(Pw + e);
+                        }
+                        if (e < total) acc += (uint32_t)x[i];
+                    }
+                }
+                if (bad) s_rf_bad = 1;
+                for (int off = (int)K; off < 64; off <<= 1) acc += (uint32_t)__shfl_xor((int)acc, off);
+                if (lane < (int)K) s_gsum[wave][lane] = acc;
+            }
+            __syncthreads();
+            if (s_rf_bad) {
+                if (tid == 0) raise_err(&ws->err, kErrTimeout);
+                alive = false;
+                break;
+            }
+            if (tid == 0) mark(QAP_PH_GRID_SYNC);
+            // wave 0: the swap costs, Eq. (2) and the first acceptance
+            if (wave == 0) {
+                uint32_t S = 0;
+                for (int i = 0; i < nwaves; ++i) S += s_gsum[i][j];
+                const uint32_t corner = ((uint32_t)arr - (uint32_t)ass) * ((uint32_t)bss - (uint32_t)brr) +
+                                        ((uint32_t)ars - (uint32_t)asr) * ((uint32_t)bsr - (uint32_t)brs);
+                const int d = (int)((SYM ? 2u * S : S) + corner);
+                bool acc = false, tie = false;
+                double z = 0.0;
+                if (lane < (int)W) {
+                    acc = d <= 0;
+                    const int32_t bound = reject_bound(temperature(temps, T0, t));
+                    if (!acc && t0_inf && inf_draw_clear(seed, chain_id, t + (uint64_t)j)) {
+                        acc = true;
+                    } else if (!acc && d <= bound) {
+                        acc = exact_test(d, temps, T0, seed, chain_id, t + (uint64_t)j, &z);
+                        tie = fabs(z) < kNearTie;
+                    }
+                }
+                const unsigned long long bal = __ballot(acc);
+                const int js = bal ? __builtin_ctzll(bal) : 64;
+                if (w == 0 && tie && j <= js) {
+                    const unsigned long long slot = atomicAdd((unsigned long long*)&ws->nties, 1ull);
+                    if (a.ties && st0.near_ties + slot < a.tie_cap)
+                        a.ties[st0.near_ties + slot] = qap_near_tie{t + (uint64_t)j, (int64_t)d, z};
+                }
+                if (lane == 0) s_key = bal ? (((unsigned long long)js << 32) | (uint32_t)__builtin_amdgcn_readlane(d, js)) : ~0ull;
+                if (bal && lane == js) {
+                    s_swap[0] = r; s_swap[1] = s;
+                    s_swap[2] = lps[s]; s_swap[3] = lps[r];   // p(u), p(v) after the swap
+                }
+            }
+            __syncthreads();
+            if (tid == 0) bump(QAP_PH_N_ROUNDS, 1);
+            const unsigned long long key = uni64(s_key);
+            if (key == ~0ull) {
+                t += W;
+                win_iters += W;
+                idx0 = uni((uint32_t)(((uint64_t)idx0 + W) % m));
+            } else {
+                const uint32_t jstar = (uint32_t)(key >> 32);
+                const int dstar = (int)(uint32_t)key;
+                const uint64_t tstar = t + jstar;
+                const int u = uni(s_swap[0]), v = uni(s_swap[1]);
+                const int pu_new = uni(s_swap[2]), pv_new = uni(s_swap[3]);
+                cost += dstar;
+                accepts += 1;
+                if (cost < best) { best = cost; best_iter = tstar + 1; }
+                if (w == 0 && tid == 0) {
+                    if (a.acc_log && accepts - 1 < a.acc_cap) {
+                        int64_t* e = a.acc_log + 4 * (accepts - 1);
+                        e[0] = (int64_t)tstar; e[1] = u; e[2] = v; e[3] = dstar;
+                    }
+                    s_rec[nrec] = Rec{tstar, ((uint32_t)u << 16) | (uint32_t)v, dstar};
+                }
+                nrec += 1;
+                // columns u, v of own rows (and rows u, v of own columns) change
+                // places; own rows u, v are read again through the new p
+                for (int lr = tid; lr < Rw; lr += nt) {
+                    const int k = w + G * lr;
+                    if (k == u || k == v) continue;
+                    E* row = lBb + lr * P;
+                    const E x = row[u];
+                    row[u] = row[v];
+                    row[v] = x;
+                    if constexpr (!SYM) {
+                        E* col = lBt + lr * P;
+                        const E y = col[u];
+                        col[u] = col[v];
+                        col[v] = y;
+                    }
+                }
+                for (int which = 0; which < 2; ++which) {
+                    const int x = which == 0 ? u : v;
+                    if (x % G != w) continue;
+                    const int px = which == 0 ? pu_new : pv_new;
+                    E* row = lBb + (x / G) * P;
+                    for (int k = tid; k < n; k += nt) {
+                        const int pk = k == u ? pu_new : (k == v ? pv_new : (int)lps[k]);
+                        row[k] = (E)((uint32_t)a.B[px * n + pk] - (uint32_t)a.b_min);
+                        if constexpr (!SYM) (lBt + (x / G) * P)[k] = gBt[(size_t)px * P + pk];   // B[p(k)][p(x)]
+                    }
+                }
+                // everyone has read p above (the swap's own rows read p(k) of k
+                // not in {u, v} only)
+                if (tid == 0) { lps[u] = (int16_t)pu_new; lps[v] = (int16_t)pv_new; }
+                t = tstar + 1;
+                win_iters += jstar + 1;
+                win_acc += 1;
+                uint32_t istar = idx0 + jstar;
+                if (istar >= m) istar -= m;
+                idx0 = istar + 1 == m ? 0 : istar + 1;
+                if (rnd) idx0 = uni((uint32_t)(t % m));   // unused in random order; kept in range
+                __syncthreads();
+                if (nrec == kRec) flush();
+                if (tid == 0) { mark(QAP_PH_SCRATCH_ACCEPT); bump(QAP_PH_N_SCRATCH_ACC, 1); }
+            }
+            if (win_iters >= 8192) {
+                // few proposals per window while most are accepted, more as acceptance falls
+                K = win_acc * 4 >= win_iters ? 4u : (win_acc * 8 >= win_iters ? 8u : 16u);
+                if (!(flags & kFlagScratchOnly) && win_acc * 1000u < win_iters * switch_permille) {
+                    if (tid == 0) bump(QAP_PH_SWITCH_T, t);
+                    break;
+                }
+                win_iters = win_acc = 0;
+            }
+        }
+        // write back: B' rows, p and the state; Delta is left stale
+        __syncthreads();
+        if (w == 0 && nrec > 0) flush();
+        for (int lr = 0; lr < Rw; ++lr) {
+            const int r = w + G * lr;
+            for (int k = tid; k < n; k += nt) a.Bp[r * n + k] = (int32_t)((uint32_t)lBb[lr * P + k] + (uint32_t)a.b_min);
+        }
+        if (w == 0) {
+            for (int i = tid; i < n; i += nt) a.p[i] = lps[i];
+            if (tid == 0) {
+                qap_chain_state st;
+                st.t = t; st.accepts = accepts; st.hash = hash;
+                st.near_ties = st0.near_ties + __hip_atomic_load((unsigned long long*)&ws->nties, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                st.cost = cost; st.best_cost = best; st.best_iter = best_iter;
+                const int err = get(&ws->err);
+                st.status = alive && err == 0 ? QAP_OK : (err == kErrTieOverflow ? QAP_E_TIE_OVERFLOW : QAP_E_TIMEOUT);
+                st.mode = QAP_MODE_SCRATCH_STALE;
+                *a.state = st;
+                mark(QAP_PH_IO);
+                bump(QAP_PH_TOTAL, clock64() - prof_start);
+            }
+            if (prof) {
+                __syncthreads();
+                if (tid < QAP_PHASES) atomicAdd((unsigned long long*)&a.prof[tid], s_prof[tid]);
+            }
+        }
+        return;
+    }
 
     while (alive && t < t_end) {
         // ------------------------------------------------------------ scan
@@ -973,13 +1226,15 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     }
 }
 
-// Slots and published values start from tag 0, which no window or update of
-// this launch uses (epochs start at 1), so nothing left by an earlier launch
-// or another chain can be taken for this launch's data.
-__global__ void k_ws_reset(DistWs* ws, unsigned long long* slots, unsigned long long* X, int nx)
+// Slots, published values and partial sums start from tag 0, which no window
+// or update of this launch uses (epochs start at 1), so nothing left by an
+// earlier launch or another chain can be taken for this launch's data.
+__global__ void k_ws_reset(DistWs* ws, unsigned long long* slots, unsigned long long* X, int nx,
+                           unsigned long long* Pp, int np)
 {
     for (int i = threadIdx.x; i < 2 * kMaxGroups; i += blockDim.x) slots[i] = 0;   // window 0 is never used
     for (int i = threadIdx.x; i < nx; i += blockDim.x) X[i] = 0;
+    for (int i = threadIdx.x; i < 2 * np; i += blockDim.x) Pp[(i >= np ? kMaxGroups * kScratchK - np : 0) + i] = 0;
     if (threadIdx.x == 0) {
         ws->err = 0;
         ws->nties = 0;
@@ -1011,8 +1266,10 @@ __global__ void k_dist_copies(int n, int P, const int32_t* __restrict__ A, const
 template <typename E>
 int launch_dist_typed(DistArgs& a, bool symmetric, int G, int threads, size_t bytes, hipStream_t stream)
 {
-    const void* fn = symmetric ? (const void*)k_chain_dist<true, E> : (const void*)k_chain_dist<false, E>;
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+    const void* fn_s = symmetric ? (const void*)k_chain_dist<true, E, true> : (const void*)k_chain_dist<false, E, true>;
+    const void* fn_d = symmetric ? (const void*)k_chain_dist<true, E, false> : (const void*)k_chain_dist<false, E, false>;
+    if (hipFuncSetAttribute(fn_s, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess ||
+        hipFuncSetAttribute(fn_d, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
         return QAP_E_DEVICE;
     if (!symmetric) {   // the copies precede the run on the same stream
         if (!a.Ab || !a.Atb || !a.Btb) return QAP_E_INVAL;
@@ -1023,11 +1280,25 @@ int launch_dist_typed(DistArgs& a, bool symmetric, int G, int threads, size_t by
                            (E*)a.Ab, (E*)a.Atb, (E*)a.Btb);
     }
     const int Rmax = (a.n + G - 1) / G;
-    hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, stream, a.ws, a.slots, a.X, 2 * 2 * G * Rmax);
-    void* kargs[] = {&a};
-    if (hipLaunchCooperativeKernel(fn, dim3(G), dim3(threads), kargs, (unsigned)bytes, stream) != hipSuccess)
-        return QAP_E_DEVICE;
-    return QAP_OK;
+    auto run = [&](const void* fn) -> int {
+        hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, stream, a.ws, a.slots, a.X, 2 * 2 * G * Rmax, a.Pp,
+                           G * kScratchK);
+        void* kargs[] = {&a};
+        if (hipLaunchCooperativeKernel(fn, dim3(G), dim3(threads), kargs, (unsigned)bytes, stream) != hipSuccess)
+            return QAP_E_DEVICE;
+        return QAP_OK;
+    };
+    // Delta mode alone: Delta rebuilt first if the chain left it stale.
+    // Otherwise scratch mode runs first (a launch that returns at once when
+    // the chain keeps Delta), and where it stopped early (acceptance fell) or
+    // at the end of the schedule Delta is rebuilt and Delta mode continues;
+    // the rebuild and the second launch read the chain state on the device
+    // and do nothing when there is nothing to do.
+    int rc = QAP_OK;
+    if (!(a.flags & kFlagDeltaOnly)) rc = run(fn_s);
+    if (rc == QAP_OK) rc = launch_delta_rebuild(a.n, a.A, a.Bp, a.delta, a.state, a.t_end, a.iters, stream);
+    if (rc == QAP_OK && !(a.flags & kFlagScratchOnly)) rc = run(fn_d);
+    return rc;
 }
 
 }  // namespace
@@ -1044,7 +1315,8 @@ int launch_chain_dist(const DistArgs& a0, bool symmetric, int esize, int G, int 
     DistArgs a = a0;
     a.quads = dist_words(a.n, esize);
     const size_t bytes = lds_dist_bytes(a.n, G, symmetric, esize);
-    if (G > kMaxGroups || threads > 512 || a.n > kMaxPerThread * threads || (a.n + G - 1) / G > kMaxOwnRows)
+    if (G > kMaxGroups || threads > 512 || threads % 64 != 0 || a.n > kMaxPerThread * threads ||
+        (a.n + G - 1) / G > kMaxOwnRows)
         return QAP_E_INVAL;
     switch (esize) {
     case 1: return launch_dist_typed<uint8_t>(a, symmetric, G, threads, bytes, stream);

@@ -84,10 +84,14 @@ static_assert(sizeof(DistWs) == 64, "workspace header");
 // 256-byte aligned after them.
 constexpr int kMaxGroups = 1024;
 inline size_t dist_row_bytes(int n, int esize) { return 4 * (((size_t)n * esize + 3) / 4); }
+// proposals of one scratch-mode window at most; the partial sums of a window
+// are exchanged through [2 parities][kMaxGroups][kScratchK] tagged entries
+constexpr int kScratchK = 16;
 inline size_t dist_ws_head(int n)
 {
     const size_t b = sizeof(DistWs) + 2 * kMaxGroups * sizeof(unsigned long long) +
-                     4 * sizeof(unsigned long long) * ((size_t)n + kMaxGroups);
+                     4 * sizeof(unsigned long long) * ((size_t)n + kMaxGroups) +
+                     2 * (size_t)kMaxGroups * kScratchK * sizeof(unsigned long long);
     return (b + 255) & ~(size_t)255;
 }
 inline size_t dist_ws_bytes(int n, bool sym, int esize)
@@ -99,6 +103,8 @@ inline unsigned long long* dist_slots(void* ws) { return (unsigned long long*)((
 // published Delta(r, u), Delta(r, v) of every row, two buffers by parity; each
 // entry is (tag << 32) | value, the tag naming the update that wrote it
 inline unsigned long long* dist_X(void* ws) { return dist_slots(ws) + 2 * kMaxGroups; }
+// scratch-mode partial sums, after the published values (sized for any n)
+inline unsigned long long* dist_P(void* ws, int n) { return dist_X(ws) + 4 * ((size_t)n + kMaxGroups); }
 
 struct DistArgs {
     int32_t n;
@@ -106,7 +112,9 @@ struct DistArgs {
     int32_t a_min, b_min;
     uint32_t kmin, kmax;         // scan window bounds (proposals)
     uint32_t random_order;       // 1: pairs drawn per iteration (QAP_FLAG_RANDOM_ORDER)
-    uint32_t pad;
+    uint32_t flags;              // QAP_FLAG_DELTA_ONLY / QAP_FLAG_SCRATCH_ONLY
+    uint32_t switch_permille;    // scratch mode ends (the kernel returns, Delta stale) below this acceptance
+    uint32_t pad2;
     uint64_t spin_limit;         // barrier polls before giving up
     const int32_t* A;
     const int32_t* B;
@@ -128,6 +136,7 @@ struct DistArgs {
     DistWs* ws;
     unsigned long long* slots;   // [2][kMaxGroups]
     unsigned long long* X;
+    unsigned long long* Pp;      // [2][kMaxGroups][kScratchK] tagged scratch-mode partial sums
     const void* Ab;              // general form: copies of A, A^T, B^T (dist_bytes)
     const void* Atb;
     const void* Btb;
@@ -138,6 +147,9 @@ struct DistArgs {
 // N = 150 asymmetric single chain over 1e8 iterations on MI355X (7-10; 20 was
 // 1.3% slower, 160 60% slower).  The threshold never changes a run's result.
 constexpr uint32_t kDefaultSwitchPermille = 10;
+// the multi-workgroup kernel's scratch mode costs about one grid-wide exchange
+// per window of up to 16 proposals, so Delta mode pays off sooner there
+constexpr uint32_t kDefaultDistSwitchPermille = 20;
 
 // element size of the multi-workgroup kernel for value ranges a_range, b_range:
 // 1 (both <= 255), 2 (<= 65535) or 4

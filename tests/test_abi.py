@@ -65,7 +65,7 @@ def test_host_side_argument_errors(qlib):
     assert Q.qap_temp_table_len(1) == 2049
     q = lambda n: (((n + 3) // 4) | 1) * 4
     for n in (2, 150):   # everything in LDS: the multi-workgroup area (asymmetric, 32-bit values) is the larger
-        head = (64 + 2 * 1024 * 8 + 32 * (n + 1024) + 255) // 256 * 256
+        head = (64 + 2 * 1024 * 8 + 32 * (n + 1024) + 2 * 1024 * 16 * 8 + 255) // 256 * 256
         assert Q.qap_workspace_bytes(n) == head + 3 * n * 4 * n
     # n = 2000: A, A^T, B', B'^T as bytes in device scratch (asymmetric chain)
     assert Q.qap_workspace_bytes(2000) == 4 * 2000 * q(2000)

@@ -31,17 +31,21 @@ def _sym(n, seed, hi=99):
     return (A + A.T).astype(np.int32), (B + B.T).astype(np.int32), rng.permutation(n).astype(np.int32)
 
 
-def _run_compare(orc, Q, A, B, p0, iters, seed, T0=None, slices=(), acc_cap=512, check_delta=True):
+def _run_compare(orc, Q, A, B, p0, iters, seed, T0=None, slices=(), acc_cap=512, check_delta=True, flags=0,
+                 switch=0):
     n = A.shape[0]
-    print(f"[case] dist n={n} iters={iters} seed={seed} T0={T0} slices={slices}", flush=True)
+    print(f"[case] dist n={n} iters={iters} seed={seed} T0={T0} slices={slices} flags={flags} switch={switch}",
+          flush=True)
     s = orc.schedule(A, B, p0, iters)
     T0o = s["T0"] if T0 is None else T0
     ref = orc.sa_run(A, B, p0, iters, T0o, s["alpha"], seed, 0, acc_cap=acc_cap, tie_cap=64)
-    c = Q.Chain(A, B, p0, iters, seed, 0, T0=T0, accept_cap=acc_cap, flags=Q.QAP_FLAG_MULTI_WG).init()
+    c = Q.Chain(A, B, p0, iters, seed, 0, T0=T0, accept_cap=acc_cap, flags=Q.QAP_FLAG_MULTI_WG | flags,
+                switch_permille=switch).init()
     for t_end in list(slices) + [iters]:
         c.run(t_end)
     got = c.result(with_delta=True)
-    assert got["status"] == 0 and got["mode"] == Q.QAP_MODE_DELTA
+    # at the end of the schedule Delta is current whichever mode the chain ended in
+    assert got["status"] == 0 and got["mode"] in (Q.QAP_MODE_SCRATCH, Q.QAP_MODE_DELTA)
     for k in ("t", "accepts", "hash", "cost", "best_cost", "best_iter", "near_ties"):
         assert got[k] == ref[k], (k, got[k], ref[k])
     assert np.array_equal(got["p"], ref["p"])
@@ -74,11 +78,13 @@ def test_dist_low_temperature(orc, Q):
     _run_compare(orc, Q, A, B, p0, 200000, seed=3, T0=1.0)
 
 
-def test_dist_n2000_prefix_golden(orc, Q):
+@pytest.mark.parametrize("flags", [0, 1])   # the library's choice (scratch mode first); Delta mode throughout
+def test_dist_n2000_prefix_golden(orc, Q, flags):
     with open(GOLD) as f:
         g = json.load(f)["n2000_sym@2000000"]
     ch = W.single_chain("n2000_sym")
-    c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id).init()
+    print(f"[case] n2000_sym prefix flags={flags}", flush=True)
+    c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id, flags=flags).init()
     assert c.sched.T0 == g["T0"] and c.sched.alpha == g["alpha"]
     assert c.info.sum_abs_delta == g["sum_abs_delta0"] and c.info.cost == g["cost0"]
     c.run(2_000_000)
@@ -87,26 +93,94 @@ def test_dist_n2000_prefix_golden(orc, Q):
         assert r[k] == g[k], (k, r[k], g[k])
     assert r["t"] == g["t_end"]
     assert r["p"].tolist() == g["p"]
-    # sampled Delta entries equal the definition at the final p
-    rng = np.random.default_rng(1)
     n = ch.n
+    rng = np.random.default_rng(1)
+    for row in rng.choice(n, 4, replace=False):
+        assert np.array_equal(r["Bp"][row], ch.B[r["p"][row]][r["p"]])
+    if r["mode"] == Q.QAP_MODE_SCRATCH_STALE:
+        return   # Delta is not kept in scratch mode
+    # sampled Delta entries equal the definition at the final p
     for _ in range(300):
         a_, b_ = sorted(rng.choice(n, 2, replace=False))
         idx = a_ * (2 * n - a_ - 1) // 2 + b_ - a_ - 1
         assert r["delta"][idx] == orc.swap_cost(ch.A, ch.B, r["p"], int(a_), int(b_))
 
 
-def test_dist_refuses_stale_delta(Q):
-    """A chain that stopped in scratch mode mid-schedule leaves Delta stale; the
-    multi-workgroup kernel, which needs Delta, reports QAP_E_STATE."""
-    A, B, p0 = _sym(220, 64)
-    c = Q.Chain(A, B, p0, 50000, 5, 0, flags=Q.QAP_FLAG_SCRATCH_ONLY).init()
+@pytest.mark.parametrize("sym", [True, False])
+def test_dist_continues_a_stale_chain(orc, Q, sym):
+    """A chain that stopped in scratch mode mid-schedule on one workgroup
+    (Delta stale) goes on over many workgroups in scratch mode, then in Delta
+    mode (Delta rebuilt first), and ends with the oracle's run."""
+    A, B, p0 = _sym(220, 64) if sym else _asym(220, 65)
+    iters = 50000
+    s = orc.schedule(A, B, p0, iters)
+    ref = orc.sa_run(A, B, p0, iters, s["T0"], s["alpha"], 5, 0, tie_cap=16)
+    c = Q.Chain(A, B, p0, iters, 5, 0, flags=Q.QAP_FLAG_SCRATCH_ONLY).init()
     c.run(1000)
     st = c.state()
     assert st.mode == Q.QAP_MODE_SCRATCH_STALE and st.status == 0
     c.sched.flags = Q.QAP_FLAG_MULTI_WG
     c.run(2000)
-    assert c.state().status == Q.QAP_E_STATE
+    st = c.state()
+    assert st.status == 0 and st.t == 2000 and st.mode == Q.QAP_MODE_SCRATCH_STALE
+    c.sched.flags = Q.QAP_FLAG_MULTI_WG | Q.QAP_FLAG_DELTA_ONLY
+    c.run(30000)
+    st = c.state()
+    assert st.status == 0 and st.mode == Q.QAP_MODE_DELTA
+    c.sched.flags = Q.QAP_FLAG_MULTI_WG
+    c.run()
+    got = c.result(with_delta=True)
+    for k in ("t", "accepts", "hash", "cost", "best_cost", "best_iter", "near_ties"):
+        assert got[k] == ref[k], (k, got[k], ref[k])
+    assert np.array_equal(got["p"], ref["p"])
+    assert np.array_equal(got["delta"], orc.delta_matrix(A, B, got["p"]))
+
+
+# (flags, switch_permille): scratch mode throughout; the default switch; a
+# switch at the first acceptance check (8192 iterations); a high threshold;
+# Delta mode throughout
+SCRATCH_MODES = [(2, 0), (0, 0), (0, 1000), (0, 300), (1, 0)]
+
+
+@pytest.mark.parametrize("flags,switch", SCRATCH_MODES)
+@pytest.mark.parametrize("sym", [True, False])
+def test_dist_modes_match_oracle(orc, Q, flags, switch, sym):
+    """Scratch mode over many workgroups (each sums its own rows' terms of a
+    window's swap costs), the switch to Delta mode (Delta rebuilt between two
+    launches) and Delta mode alone give the same run, across slices that cut
+    windows and the switch."""
+    n = 250
+    A, B, p0 = _sym(n, 66) if sym else _asym(n, 67)
+    _run_compare(orc, Q, A, B, p0, 40000, seed=8, flags=flags, switch=switch,
+                 slices=(1, 5000, 8193, 8194, 20000))
+
+
+@pytest.mark.parametrize("sym", [True, False])
+def test_dist_scratch_mode_state(orc, Q, sym):
+    """Mode after a slice: scratch mode leaves Delta stale while the chain
+    accepts often; a threshold of 1000 per 1000 moves it to Delta mode at the
+    first check, with Delta rebuilt for the current p."""
+    n = 230
+    A, B, p0 = _sym(n, 68) if sym else _asym(n, 69)
+    c = Q.Chain(A, B, p0, 100000, 4, 0, flags=Q.QAP_FLAG_MULTI_WG).init()
+    c.run(5000)
+    assert c.state().mode == Q.QAP_MODE_SCRATCH_STALE
+    c2 = Q.Chain(A, B, p0, 100000, 4, 0, flags=Q.QAP_FLAG_MULTI_WG, switch_permille=1000).init()
+    c2.run(20000)
+    got = c2.result(with_delta=True)
+    assert got["mode"] == Q.QAP_MODE_DELTA and got["t"] == 20000
+    assert np.array_equal(got["delta"], orc.delta_matrix(A, B, got["p"]))
+    c.run(20000)
+    assert c.result()["hash"] == got["hash"]
+
+
+@pytest.mark.parametrize("sym", [True, False])
+def test_dist_scratch_mode_infinite_temperature(orc, Q, sym):
+    """Every proposal accepted in scratch mode: the window's first proposal is
+    made each time and rows u, v of B' are read again through p."""
+    A, B, p0 = _sym(300, 70) if sym else _asym(300, 71)
+    got = _run_compare(orc, Q, A, B, p0, 3000, seed=1, T0=math.inf, acc_cap=3000, flags=Q.QAP_FLAG_SCRATCH_ONLY)
+    assert got["accepts"] == 3000
 
 
 def _asym(n, seed, hi=99):
@@ -145,11 +219,13 @@ def test_dist_general_form_sparse_grid(orc, Q):
     _run_compare(orc, Q, A, B, p0, 40000, seed=4)
 
 
-def test_dist_general_form_n2000_prefix_golden(orc, Q):
+@pytest.mark.parametrize("flags", [0, 1])
+def test_dist_general_form_n2000_prefix_golden(orc, Q, flags):
     with open(GOLD) as f:
         g = json.load(f)["n2000_asym@300000"]
     ch = W.single_chain("n2000_asym")
-    c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id).init()
+    print(f"[case] n2000_asym prefix flags={flags}", flush=True)
+    c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id, flags=flags).init()
     assert c.sched.T0 == g["T0"] and c.sched.alpha == g["alpha"]
     c.run(100_000)
     c.run(300_000)
@@ -159,6 +235,10 @@ def test_dist_general_form_n2000_prefix_golden(orc, Q):
     assert r["t"] == g["t_end"] and r["p"].tolist() == g["p"]
     rng = np.random.default_rng(2)
     n = ch.n
+    for row in rng.choice(n, 4, replace=False):
+        assert np.array_equal(r["Bp"][row], ch.B[r["p"][row]][r["p"]])
+    if r["mode"] == Q.QAP_MODE_SCRATCH_STALE:
+        return
     for _ in range(100):
         a_, b_ = sorted(rng.choice(n, 2, replace=False))
         idx = a_ * (2 * n - a_ - 1) // 2 + b_ - a_ - 1

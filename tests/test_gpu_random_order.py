@@ -111,7 +111,7 @@ def _sym(n, seed, hi=99):
 def test_multi_workgroup_matches_oracle(orc, Q, n, iters):
     A, B, p0 = _sym(n, 7300 + n)
     got, _ = _compare(orc, Q, A, B, p0, iters, seed=11 + n, flags=Q.QAP_FLAG_MULTI_WG, slices=(4321,))
-    assert got["mode"] == Q.QAP_MODE_DELTA
+    assert got["mode"] in (Q.QAP_MODE_SCRATCH, Q.QAP_MODE_DELTA)
 
 
 def test_multi_workgroup_infinite_temperature(orc, Q):
@@ -174,14 +174,38 @@ def test_n150_full_schedule_against_stored_oracle_run(orc, Q):
     _sampled_delta(orc, ch, r, 200, 2)
 
 
-def test_n2000_prefix_against_stored_oracle_run(orc, Q):
+@pytest.mark.parametrize("flags", [0, 1])   # the library's choice (scratch mode first); Delta mode throughout
+def test_n2000_prefix_against_stored_oracle_run(orc, Q, flags):
     """N = 2000 symmetric on the multi-workgroup kernel, random order, first 3e5
     iterations of the I = 1e9 schedule."""
     g = _golden("n2000_sym@300000:random")
     ch = W.single_chain("n2000_sym")
-    c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id, flags=Q.QAP_FLAG_RANDOM_ORDER).init()
+    print(f"[case] n2000_sym random order prefix flags={flags}", flush=True)
+    c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id,
+                flags=Q.QAP_FLAG_RANDOM_ORDER | flags).init()
     assert c.sched.T0 == g["T0"] and c.sched.alpha == g["alpha"]
     c.run(300_000)
     r = c.result(with_delta=True)
     _check_state(r, g)
-    _sampled_delta(orc, ch, r, 300, 3)
+    rows = np.random.default_rng(4).choice(ch.n, 4, replace=False)
+    for row in rows:
+        assert np.array_equal(r["Bp"][row], ch.B[r["p"][row]][r["p"]])
+    if r["mode"] != Q.QAP_MODE_SCRATCH_STALE:   # Delta is not kept in scratch mode
+        _sampled_delta(orc, ch, r, 300, 3)
+
+
+@pytest.mark.parametrize("flags,switch", [(2, 0), (0, 1000), (1, 0)])
+@pytest.mark.parametrize("sym", [True, False])
+def test_multi_workgroup_modes_random_order(orc, Q, flags, switch, sym):
+    """Random proposal order over many workgroups in scratch mode, across the
+    switch, and in Delta mode."""
+    n = 240
+    if sym:
+        A, B, p0 = _sym(n, 7500)
+    else:
+        rng = np.random.default_rng(7501)
+        A = rng.integers(0, 100, (n, n)).astype(np.int32)
+        B = rng.integers(0, 100, (n, n)).astype(np.int32)
+        p0 = rng.permutation(n).astype(np.int32)
+    _compare(orc, Q, A, B, p0, 30000, seed=13, flags=Q.QAP_FLAG_MULTI_WG | flags, switch=switch,
+             slices=(3, 9000, 9001))

@@ -84,3 +84,17 @@ def test_wide_values_infinite_and_low_temperature(orc, Q):
     got = _compare(orc, Q, A, B, p0, 3000, seed=1, T0=math.inf, acc_cap=3000)
     assert got["accepts"] == 3000
     _compare(orc, Q, A, B, p0, 100000, seed=2, T0=1.0)
+
+
+# odd n with 16-bit words: the general form's own rows and columns of A do not
+# fit the LDS of the Delta rows in scratch mode and are read from device memory
+MODE_CASES = [(301, False, (0, 999), (0, 999)), (300, False, (0, 999), (0, 999)),
+              (300, False, (-50000, 49999), (0, 20)), (260, True, (0, 99999), (-10, 9))]
+
+
+@pytest.mark.parametrize("mode", ["scratch", "delta"])
+@pytest.mark.parametrize("n,sym,ar,br", MODE_CASES)
+def test_wide_values_scratch_and_delta_modes(orc, Q, n, sym, ar, br, mode):
+    A, B, p0 = _inst(n, 7100 + n, sym, *ar, *br)
+    flags = Q.QAP_FLAG_MULTI_WG | (Q.QAP_FLAG_SCRATCH_ONLY if mode == "scratch" else Q.QAP_FLAG_DELTA_ONLY)
+    _compare(orc, Q, A, B, p0, 20000, seed=5 + n, flags=flags, slices=(1, 5000))
