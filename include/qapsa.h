@@ -125,7 +125,7 @@ typedef struct {
     uint32_t switch_permille; /* a chain in scratch mode moves to Delta mode when fewer
                             than this many proposals per 1000 were accepted over the
                             last 8192 iterations; 0 selects the default (10 on one
-                            workgroup, 20 over many workgroups)                        */
+                            workgroup, 30 over many workgroups)                        */
     uint32_t scan_window; /* the size of the subset of proposals tested at once against
                             the unchanged Delta (Sec. 3 (ii), an adjustable parameter):
                             multi-workgroup kernel, proposals in the first window after

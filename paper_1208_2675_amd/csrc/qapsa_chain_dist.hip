@@ -167,6 +167,7 @@ struct Lds {
     char* abp;
     char* bbp;
     int16_t* ps;     // [n]
+    int32_t* dg;     // [2][n] diagonals of A and B (scratch mode, in the Delta rows' space)
 };
 
 __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -181,7 +182,11 @@ __host__ __device__ inline size_t dist_layout(int n, int G, int q, int esize, bo
     const size_t pw = esize == 1 ? 4 : 8;                          // bytes of one difference pair
     size_t off = 0;
     auto take = [&](size_t b) { char* p = base ? base + off : nullptr; off = a16(off + b); return p; };
-    char* d = take(4 * R * n);
+    // Scratch mode keeps no Delta; its space holds the general form's own rows
+    // and columns of A (when they fit) and the diagonals of A and B.
+    const size_t a_off = (!sym && 2 * P <= 4 * (size_t)n) ? a16(2 * R * P) : 0;
+    const size_t d_bytes = 4 * R * n > a_off + 8 * (size_t)n ? 4 * R * n : a_off + 8 * (size_t)n;
+    char* d = take(d_bytes);
     char* ab = sym ? take(R * P) : nullptr;
     char* bb = take(R * P);
     char* bt = sym ? nullptr : take(R * P);
@@ -201,6 +206,7 @@ __host__ __device__ inline size_t dist_layout(int n, int G, int q, int esize, bo
         L->Su = su; L->Sv = sv; L->Tu = tu; L->Tv = tv;
         L->Scu = scu; L->Scv = scv; L->Tcu = tcu; L->Tcv = tcv;
         L->abp = abp; L->bbp = bbp; L->ps = (int16_t*)ps;
+        L->dg = (int32_t*)(d + a_off);
     }
     return off;
 }
@@ -262,6 +268,28 @@ __device__ __noinline__ bool exact_test(int d, const double* temps, double T0, u
                                         uint64_t t, double* z)
 {
     return metropolis_positive(d, temperature(temps, T0, t), uniform_r(seed, chain, t), z);
+}
+// The three cooling-table entries of T_t, read apart from the products that
+// make T_t (temperature()) so that their latency can overlap other work.
+struct TempParts {
+    double h, m, l;
+};
+__device__ __forceinline__ TempParts temp_parts(const double* __restrict__ temps, uint64_t t)
+{
+    return TempParts{temps[2048 + (t >> 20)], temps[1024 + ((t >> 10) & 1023u)], temps[t & 1023u]};
+}
+// T_t from its table entries, in the order temperature() multiplies them
+__device__ __forceinline__ double temp_of(double T0, const TempParts& p) { return ((T0 * p.h) * p.m) * p.l; }
+
+// The pair `steps` places after (r, s) in the cyclic row-major order.
+__device__ __forceinline__ void advance_pair(int n, int& r, int& s, int steps)
+{
+    s += steps;
+    while (s >= n) {
+        const int off = s - n;
+        r = r + 1 == n - 1 ? 0 : r + 1;
+        s = r + 1 + off;
+    }
 }
 
 // SCR: the scratch-mode instantiation (returns at once when the chain is to
@@ -385,6 +413,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         const int pi = a.p[i];
         if (pi < 0 || pi >= n) s_ok = 0;   // p indexes B below
         lps[i] = (int16_t)pi;
+        if (scr) { L_.dg[i] = a.A[i * n + i]; L_.dg[n + i] = a.B[i * n + i]; }
     }
     __syncthreads();
     if (!s_ok || (!scr && st0.mode == QAP_MODE_SCRATCH_STALE)) {
@@ -573,36 +602,106 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         uint64_t win_iters = 0, win_acc = 0;
         const uint32_t flags = a.flags, switch_permille = a.switch_permille;
         unsigned long long* const Pbase = a.Pp;
+        const int32_t* const ldA = L_.dg;         // diagonal of A
+        const int32_t* const ldB = L_.dg + n;     // diagonal of B
+        // Rows of B' read ahead, so that a swap does not wait for them: the
+        // owner of the v of a candidate (r0, v) reads row (and column) r0,
+        // which becomes row v when (r0, v) is accepted (two entries change
+        // places); the owner of u of an accepted swap reads its new row u and
+        // writes it in the next window, before the row is first needed.  One
+        // element of each of this thread's columns k = tid + i * nt.
+        uint32_t sp_row[kMaxPerThread], sp_col[kMaxPerThread];
+        uint32_t pd_row[kMaxPerThread], pd_col[kMaxPerThread];
+        int spec_r = -1;    // row read ahead into sp_*, or -1
+        int pend = -1;      // own row whose new content waits in pd_*, or -1
+        // row x of B' (and column x, general form) from registers; the
+        // entries at ua and va change places (none when ua < 0)
+        auto write_row = [&](int x, const uint32_t* vr, const uint32_t* vc, int ua, int va)
+            __attribute__((always_inline)) {
+            E* row = lBb + (x / G) * P;
+#pragma unroll
+            for (int i = 0; i < kMaxPerThread; ++i) {
+                if (i >= nk) break;
+                const int k = tid + i * nt;
+                if (k >= n) continue;
+                const int dst = k == ua ? va : (k == va ? ua : k);
+                row[dst] = (E)vr[i];
+                if constexpr (!SYM) (lBt + (x / G) * P)[dst] = (E)vc[i];
+            }
+        };
+        // row x of B' after the swap (u, v) (p' = p o (u v)), read through p':
+        // B'[x][k] = B[p'(x)][p'(k)], and column x, B[p'(k)][p'(x)]
+        auto read_row = [&](int px, int u, int v, int pu_new, int pv_new, uint32_t* vr, uint32_t* vc)
+            __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < kMaxPerThread; ++i) {
+                if (i >= nk) break;
+                const int k = min(tid + i * nt, n - 1);
+                const int pk = k == u ? pu_new : (k == v ? pv_new : (int)lps[k]);
+                vr[i] = (uint32_t)a.B[px * n + pk] - (uint32_t)a.b_min;
+                if constexpr (!SYM) vc[i] = gBt[(size_t)px * P + pk];
+            }
+        };
         while (alive && t < t_end) {
             const uint32_t W = (uint32_t)min<uint64_t>(min<uint64_t>((uint64_t)K, t_end - t), (uint64_t)m);
             epoch += 1;
             const uint32_t tag = (uint32_t)epoch;
             unsigned long long* const Pw = Pbase + (size_t)(epoch & 1) * kMaxGroups * kScratchK;
+            // which rows of this workgroup the window needs: the pending row is
+            // needed by proposals (r, s) with r not that row; a candidate (r0, v)
+            // with v owned here has row r0 read ahead
+            bool spec = false, need_pend = pend >= 0 && rnd;
+            if (!rnd) {
+                int rr = r0, ss = s0;
+                for (uint32_t jj = 0; jj < W; ++jj) {
+                    if (jj) advance_pair(n, rr, ss, 1);
+                    if (rr == r0 && ss % G == w) spec = true;
+                    if (pend >= 0 && rr != pend) need_pend = true;
+                }
+            }
+            if (need_pend) {
+                write_row(pend, pd_row, pd_col, -1, -1);
+                pend = -1;
+                __syncthreads();
+            }
+            if (spec) read_row((int)lps[r0], -1, -1, 0, 0, sp_row, sp_col);   // old row r0, current p
+            spec_r = spec ? r0 : -1;
             // wave 0: this workgroup's partial sums, one proposal per lane j < K
-            // (lanes j, j + K, ... split the own rows), and the loads of the
-            // entries of A and B that enter through both indices
+            // (lanes j, j + K, ... split the own rows).  The owner of row s
+            // adds the two terms with both indices in {r, s}; the symmetric
+            // form counts each row term twice (rows and columns alike).
             const int j = lane & (int)(K - 1);
-            int r = 0, s = 1;
-            int32_t arr = 0, ass = 0, ars = 0, asr = 0, brr = 0, bss = 0, brs = 0, bsr = 0;
+            int r = r0, s = s0;
+            TempParts tp{0.0, 0.0, 0.0};
+            double ylog = 0.0;
             if (wave == 0) {
-                uint32_t idx = idx0 + (uint32_t)j;
-                if (idx >= m) idx -= m;
-                if (rnd) idx = random_pair_index(seed, chain_id, t + (uint64_t)j, m);
-                pair_of_u(n, idx, r, s);
+                if (rnd) pair_of_u(n, random_pair_index(seed, chain_id, t + (uint64_t)j, m), r, s);
+                else advance_pair(n, r, s, j);
+                if ((uint32_t)j < W) tp = temp_parts(temps, t + (uint64_t)j);   // read now, used after the exchange
                 uint32_t part = 0;   // modulo 2^32 (see Elem)
                 if ((uint32_t)j < W) {
+                    const int pr = lps[r], ps = lps[s];
                     for (int lr = lane / (int)K; lr < Rw; lr += 64 / (int)K) {
                         const int k = w + G * lr;
-                        if (k == r || k == s) continue;
+                        if (k == r) continue;
                         const E* Bk = lBb + lr * P;   // row k of B'
                         if constexpr (SYM) {
                             const E* Ak = lAb + lr * P;
-                            part += ((uint32_t)Ak[r] - (uint32_t)Ak[s]) * ((uint32_t)Bk[s] - (uint32_t)Bk[r]);
+                            if (k == s) {
+                                part += ((uint32_t)ldA[r] - (uint32_t)ldA[s]) * ((uint32_t)ldB[ps] - (uint32_t)ldB[pr]);
+                                continue;
+                            }
+                            part += 2u * (((uint32_t)Ak[r] - (uint32_t)Ak[s]) * ((uint32_t)Bk[s] - (uint32_t)Bk[r]));
                         } else {
                             // row k of A, column k of A (Ck[x] = A[x][k]) and column k of B' (Dk[x] = B'[x][k])
                             const E* Ak = a_lds ? lAr + lr * P : gA + (size_t)k * P;
                             const E* Ck = a_lds ? lAc + lr * P : gAt + (size_t)k * P;
                             const E* Dk = lBt + lr * P;
+                            if (k == s) {
+                                part += ((uint32_t)ldA[r] - (uint32_t)ldA[s]) * ((uint32_t)ldB[ps] - (uint32_t)ldB[pr]);
+                                part += ((uint32_t)Ck[r] - (uint32_t)Ak[r]) * ((uint32_t)Bk[r] - (uint32_t)Dk[r]);
+                                continue;
+                            }
                             part += ((uint32_t)Ak[r] - (uint32_t)Ak[s]) * ((uint32_t)Bk[s] - (uint32_t)Bk[r]);
                             part += ((uint32_t)Ck[r] - (uint32_t)Ck[s]) * ((uint32_t)Dk[s] - (uint32_t)Dk[r]);
                         }
@@ -610,11 +709,13 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 }
                 for (int off = (int)K; off < 64; off <<= 1) part += (uint32_t)__shfl_xor((int)part, off);
                 if (lane < (int)K) put64(Pw + w * K + lane, ((unsigned long long)tag << 32) | part);
-                if (lane < (int)K && (uint32_t)j < W) {
-                    const int pr = lps[r], ps = lps[s];
-                    arr = a.A[r * n + r]; ass = a.A[s * n + s]; ars = a.A[r * n + s]; asr = a.A[s * n + r];
-                    brr = a.B[pr * n + pr]; bss = a.B[ps * n + ps]; brs = a.B[pr * n + ps]; bsr = a.B[ps * n + pr];
-                }
+                // log r_t of Eq. (2) while the exchange runs
+                if ((uint32_t)j < W && !t0_inf) ylog = log(uniform_r(seed, chain_id, t + (uint64_t)j));
+            }
+            // the pending row, not read by this window's partials, lands now
+            if (pend >= 0) {
+                write_row(pend, pd_row, pd_col, -1, -1);
+                pend = -1;
             }
             if (tid == 0) mark(QAP_PH_SCRATCH_EVAL);
             // every workgroup's partials of this window (thread tid takes
@@ -657,18 +758,18 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             if (wave == 0) {
                 uint32_t S = 0;
                 for (int i = 0; i < nwaves; ++i) S += s_gsum[i][j];
-                const uint32_t corner = ((uint32_t)arr - (uint32_t)ass) * ((uint32_t)bss - (uint32_t)brr) +
-                                        ((uint32_t)ars - (uint32_t)asr) * ((uint32_t)bsr - (uint32_t)brs);
-                const int d = (int)((SYM ? 2u * S : S) + corner);
+                const int d = (int)S;
                 bool acc = false, tie = false;
                 double z = 0.0;
                 if (lane < (int)W) {
                     acc = d <= 0;
-                    const int32_t bound = reject_bound(temperature(temps, T0, t));
+                    const double Tj = temp_of(T0, tp);
                     if (!acc && t0_inf && inf_draw_clear(seed, chain_id, t + (uint64_t)j)) {
                         acc = true;
-                    } else if (!acc && d <= bound) {
-                        acc = exact_test(d, temps, T0, seed, chain_id, t + (uint64_t)j, &z);
+                    } else if (!acc && d <= reject_bound(Tj)) {
+                        if (t0_inf) ylog = log(uniform_r(seed, chain_id, t + (uint64_t)j));
+                        z = (double)d / Tj + ylog;   // the operations of metropolis_positive
+                        acc = z < 0.0;
                         tie = fabs(z) < kNearTie;
                     }
                 }
@@ -691,7 +792,9 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             if (key == ~0ull) {
                 t += W;
                 win_iters += W;
-                idx0 = uni((uint32_t)(((uint64_t)idx0 + W) % m));
+                advance_pair(n, r0, s0, (int)W);
+                r0 = uni(r0);
+                s0 = uni(s0);
             } else {
                 const uint32_t jstar = (uint32_t)(key >> 32);
                 const int dstar = (int)(uint32_t)key;
@@ -709,8 +812,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                     s_rec[nrec] = Rec{tstar, ((uint32_t)u << 16) | (uint32_t)v, dstar};
                 }
                 nrec += 1;
-                // columns u, v of own rows (and rows u, v of own columns) change
-                // places; own rows u, v are read again through the new p
+                // columns u, v of own rows (and rows u, v of own columns) change places
                 for (int lr = tid; lr < Rw; lr += nt) {
                     const int k = w + G * lr;
                     if (k == u || k == v) continue;
@@ -725,27 +827,31 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                         col[v] = y;
                     }
                 }
-                for (int which = 0; which < 2; ++which) {
-                    const int x = which == 0 ? u : v;
-                    if (x % G != w) continue;
-                    const int px = which == 0 ? pu_new : pv_new;
-                    E* row = lBb + (x / G) * P;
-                    for (int k = tid; k < n; k += nt) {
-                        const int pk = k == u ? pu_new : (k == v ? pv_new : (int)lps[k]);
-                        row[k] = (E)((uint32_t)a.B[px * n + pk] - (uint32_t)a.b_min);
-                        if constexpr (!SYM) (lBt + (x / G) * P)[k] = gBt[(size_t)px * P + pk];   // B[p(k)][p(x)]
+                // own row v: the row read ahead (old row u, entries u and v
+                // exchanged) when it is this window's, else read now; own row
+                // u: read now, written in the next window.  Neither reads p at
+                // u or v, which thread 0 changes meanwhile.
+                if (v % G == w) {
+                    if (spec_r == u) {
+                        write_row(v, sp_row, sp_col, u, v);
+                    } else {
+                        read_row(pv_new, u, v, pu_new, pv_new, sp_row, sp_col);
+                        write_row(v, sp_row, sp_col, -1, -1);
                     }
                 }
-                // everyone has read p above (the swap's own rows read p(k) of k
-                // not in {u, v} only)
+                if (u % G == w) {
+                    read_row(pu_new, u, v, pu_new, pv_new, pd_row, pd_col);
+                    pend = u;
+                }
                 if (tid == 0) { lps[u] = (int16_t)pu_new; lps[v] = (int16_t)pv_new; }
                 t = tstar + 1;
                 win_iters += jstar + 1;
                 win_acc += 1;
-                uint32_t istar = idx0 + jstar;
-                if (istar >= m) istar -= m;
-                idx0 = istar + 1 == m ? 0 : istar + 1;
-                if (rnd) idx0 = uni((uint32_t)(t % m));   // unused in random order; kept in range
+                r0 = u;
+                s0 = v;
+                advance_pair(n, r0, s0, 1);
+                r0 = uni(r0);
+                s0 = uni(s0);
                 __syncthreads();
                 if (nrec == kRec) flush();
                 if (tid == 0) { mark(QAP_PH_SCRATCH_ACCEPT); bump(QAP_PH_N_SCRATCH_ACC, 1); }
@@ -760,6 +866,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 win_iters = win_acc = 0;
             }
         }
+        if (pend >= 0) write_row(pend, pd_row, pd_col, -1, -1);
         // write back: B' rows, p and the state; Delta is left stale
         __syncthreads();
         if (w == 0 && nrec > 0) flush();

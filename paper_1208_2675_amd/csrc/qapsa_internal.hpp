@@ -149,7 +149,7 @@ struct DistArgs {
 constexpr uint32_t kDefaultSwitchPermille = 10;
 // the multi-workgroup kernel's scratch mode costs about one grid-wide exchange
 // per window of up to 16 proposals, so Delta mode pays off sooner there
-constexpr uint32_t kDefaultDistSwitchPermille = 20;
+constexpr uint32_t kDefaultDistSwitchPermille = 30;
 
 // element size of the multi-workgroup kernel for value ranges a_range, b_range:
 // 1 (both <= 255), 2 (<= 65535) or 4
