@@ -565,7 +565,9 @@ def section_config2(Q, W, torch, args):
                        "acceptance": acc / (t_end - t), "cost": int(st.cost),
                        "scan_steps": d["n_scan_steps"], "scanned": d["n_scanned"],
                        "cycles_scan": d["delta_scan"], "cycles_sync": d["grid_sync"],
-                       "cycles_update": d["delta_update"]})
+                       "cycles_update": d["delta_update"], "scratch_windows": d["n_rounds"],
+                       "scratch_accepts": d["n_scratch_acc"], "cycles_scratch_eval": d["scratch_eval"],
+                       "cycles_scratch_accept": d["scratch_accept"]})
         t = t_end
         for tp, key in prefix_keys:
             if t == tp:

@@ -87,6 +87,19 @@ __device__ __forceinline__ int wave_sum(int v)
     return __builtin_amdgcn_readlane(v, 63);
 }
 
+// Sum over the lanes with the same lane mod K (K = 4, 8 or 16), returned to
+// every lane: rotations within 16-lane rows, then v_permlane16_swap and
+// v_permlane32_swap fold the rows (no LDS round trips).
+__device__ __forceinline__ uint32_t stride_sum(uint32_t v, uint32_t K)
+{
+    if (K <= 4) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false);   // row_ror:4
+    if (K <= 8) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false);   // row_ror:8
+    const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = a[0] + a[1];
+    const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return b[0] + b[1];
+}
+
 __device__ __forceinline__ unsigned long long wave_min64(unsigned long long v)
 {
     for (int off = 32; off > 0; off >>= 1) {
@@ -604,6 +617,10 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         unsigned long long* const Pbase = a.Pp;
         const int32_t* const ldA = L_.dg;         // diagonal of A
         const int32_t* const ldB = L_.dg + n;     // diagonal of B
+        // Every workgroup writes its partial sums to `reps` copies and reads
+        // copy w mod reps: fewer readers per line (7% faster at N = 2000 with
+        // four copies than with one)
+        const int reps = scratch_reps(G);
         // Rows of B' read ahead, so that a swap does not wait for them: the
         // owner of the v of a candidate (r0, v) reads row (and column) r0,
         // which becomes row v when (r0, v) is accepted (two entries change
@@ -707,8 +724,9 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                         }
                     }
                 }
-                for (int off = (int)K; off < 64; off <<= 1) part += (uint32_t)__shfl_xor((int)part, off);
-                if (lane < (int)K) put64(Pw + w * K + lane, ((unsigned long long)tag << 32) | part);
+                part = stride_sum(part, K);
+                if (lane < (int)K)
+                    for (int rr = 0; rr < reps; ++rr) put64(Pw + rr * G * K + w * K + lane, ((unsigned long long)tag << 32) | part);
                 // log r_t of Eq. (2) while the exchange runs
                 if ((uint32_t)j < W && !t0_inf) ylog = log(uniform_r(seed, chain_id, t + (uint64_t)j));
             }
@@ -722,6 +740,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             // proposal tid mod K: the block size is a multiple of K)
             {
                 const int total = G * (int)K;
+                unsigned long long* const Pr = Pw + (w % reps) * total;
                 uint32_t acc = 0;
                 bool bad = false;
                 for (int e0 = tid; e0 < total && !bad; e0 += 8 * nt) {
@@ -729,7 +748,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
                         const int e = e0 + i * nt;
-                        x[i] = e < total ? get64(Pw + e) : ((unsigned long long)tag << 32);
+                        x[i] = e < total ? get64(Pr + e) : ((unsigned long long)tag << 32);
                     }
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
@@ -738,13 +757,13 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                         while (!bad && (uint32_t)(x[i] >> 32) != tag) {
                             if (++spins > spin_limit || ((spins & 63) == 0 && get(&ws->err))) { bad = true; break; }
                             __builtin_amdgcn_s_sleep(1);
-                            x[i] = get64(Pw + e);
+                            x[i] = get64(Pr + e);
                         }
                         if (e < total) acc += (uint32_t)x[i];
                     }
                 }
                 if (bad) s_rf_bad = 1;
-                for (int off = (int)K; off < 64; off <<= 1) acc += (uint32_t)__shfl_xor((int)acc, off);
+                acc = stride_sum(acc, K);
                 if (lane < (int)K) s_gsum[wave][lane] = acc;
             }
             __syncthreads();
@@ -1389,7 +1408,7 @@ int launch_dist_typed(DistArgs& a, bool symmetric, int G, int threads, size_t by
     const int Rmax = (a.n + G - 1) / G;
     auto run = [&](const void* fn) -> int {
         hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, stream, a.ws, a.slots, a.X, 2 * 2 * G * Rmax, a.Pp,
-                           G * kScratchK);
+                           scratch_reps(G) * G * kScratchK);
         void* kargs[] = {&a};
         if (hipLaunchCooperativeKernel(fn, dim3(G), dim3(threads), kargs, (unsigned)bytes, stream) != hipSuccess)
             return QAP_E_DEVICE;

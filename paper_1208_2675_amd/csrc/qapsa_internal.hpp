@@ -85,8 +85,10 @@ static_assert(sizeof(DistWs) == 64, "workspace header");
 constexpr int kMaxGroups = 1024;
 inline size_t dist_row_bytes(int n, int esize) { return 4 * (((size_t)n * esize + 3) / 4); }
 // proposals of one scratch-mode window at most; the partial sums of a window
-// are exchanged through [2 parities][kMaxGroups][kScratchK] tagged entries
+// are exchanged through [2 parities][kMaxGroups * kScratchK] tagged entries,
+// each parity holding scratch_reps(G) copies of G * K entries
 constexpr int kScratchK = 16;
+__host__ __device__ inline int scratch_reps(int G) { return G <= kMaxGroups / 4 ? 4 : (G <= kMaxGroups / 2 ? 2 : 1); }
 inline size_t dist_ws_head(int n)
 {
     const size_t b = sizeof(DistWs) + 2 * kMaxGroups * sizeof(unsigned long long) +
