@@ -103,7 +103,7 @@ QAP_API uint64_t qap_workspace_bytes(int32_t n)
     size_t bytes = dist_ws_bytes(n, false, 1);
     for (int esize = 1; esize <= 4; esize *= 2)
         for (int sym = 0; sym < 2; ++sym)
-            if (lds_dist_bytes(n, 256, sym != 0, esize) <= kLdsLimit - kLdsStaticReserve) {
+            if (lds_dist_bytes(n, 256, sym != 0, esize) <= kLdsLimit - kDistStaticReserve) {
                 const size_t b = dist_ws_bytes(n, sym != 0, esize);
                 if (b > bytes) bytes = b;
             }
@@ -229,8 +229,9 @@ int sa_run_impl(int32_t n, const int32_t* A, const int32_t* B, int32_t* Bp, int3
         int G = (n + 7) / 8;                 // about eight rows per workgroup
         if (G > cus) G = cus;
         if (G < 2) G = 2;
-        while (G < cus && lds_dist_bytes(n, G, sym, esize) > budget) ++G;
-        if (lds_dist_bytes(n, G, sym, esize) <= budget) {
+        const size_t dbudget = kLdsLimit - kDistStaticReserve;
+        while (G < cus && lds_dist_bytes(n, G, sym, esize) > dbudget) ++G;
+        if (lds_dist_bytes(n, G, sym, esize) <= dbudget) {
             if (!bufs->workspace) return QAP_E_INVAL;
             if (bufs->workspace_bytes < dist_ws_bytes(n, sym, esize)) return ws_short;
             DistArgs d{};

@@ -180,7 +180,10 @@ struct Lds {
     char* abp;
     char* bbp;
     int16_t* ps;     // [n]
-    int32_t* dg;     // [2][n] diagonals of A and B (scratch mode, in the Delta rows' space)
+    // scratch-mode launches (no Delta rows, no staging)
+    char* Ar;        // [R][P] own rows of A - a_min (general form)
+    char* Ac;        // [R][P] own columns of A - a_min (general form)
+    int32_t* dg;     // [2][n] diagonals of A and B
 };
 
 __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -188,18 +191,32 @@ __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15;
 // LDS layout of one workgroup.  The general (asymmetric) form keeps its own
 // columns of B' beside its rows and stages columns u, v as well as rows; its
 // rows and columns of A are read from byte copies in device memory instead
-// (they never change), so that N = 2000 still fits one CU's LDS.
-__host__ __device__ inline size_t dist_layout(int n, int G, int q, int esize, bool sym, char* base, Lds* L)
+// (they never change), so that N = 2000 still fits one CU's LDS.  A
+// scratch-mode launch keeps no Delta and stages nothing: its own rows (and
+// columns) of A and B', the diagonals of A and B, and p.
+__host__ __device__ inline size_t dist_layout(int n, int G, int q, int esize, bool sym, bool scratch, char* base,
+                                              Lds* L)
 {
     const size_t R = (size_t)(n + G - 1) / G, P = 4 * (size_t)q;   // P: row bytes here
     const size_t pw = esize == 1 ? 4 : 8;                          // bytes of one difference pair
     size_t off = 0;
     auto take = [&](size_t b) { char* p = base ? base + off : nullptr; off = a16(off + b); return p; };
-    // Scratch mode keeps no Delta; its space holds the general form's own rows
-    // and columns of A (when they fit) and the diagonals of A and B.
-    const size_t a_off = (!sym && 2 * P <= 4 * (size_t)n) ? a16(2 * R * P) : 0;
-    const size_t d_bytes = 4 * R * n > a_off + 8 * (size_t)n ? 4 * R * n : a_off + 8 * (size_t)n;
-    char* d = take(d_bytes);
+    if (scratch) {
+        char* ab = sym ? take(R * P) : nullptr;
+        char* ar = sym ? nullptr : take(R * P);
+        char* ac = sym ? nullptr : take(R * P);
+        char* bb = take(R * P);
+        char* bt = sym ? nullptr : take(R * P);
+        char* dg = take(8 * (size_t)n);
+        char* ps = take(2 * (size_t)n);
+        if (L) {
+            *L = Lds{};
+            L->Ab = ab; L->Ar = ar; L->Ac = ac; L->Bb = bb; L->Bt = bt;
+            L->dg = (int32_t*)dg; L->ps = (int16_t*)ps;
+        }
+        return off;
+    }
+    char* d = take(4 * R * n);
     char* ab = sym ? take(R * P) : nullptr;
     char* bb = take(R * P);
     char* bt = sym ? nullptr : take(R * P);
@@ -215,11 +232,11 @@ __host__ __device__ inline size_t dist_layout(int n, int G, int q, int esize, bo
     char* bbp = take(pw * (size_t)n);
     char* ps = take(2 * (size_t)n);
     if (L) {
+        *L = Lds{};
         L->D = (int32_t*)d; L->Ab = ab; L->Bb = bb; L->Bt = bt;
         L->Su = su; L->Sv = sv; L->Tu = tu; L->Tv = tv;
         L->Scu = scu; L->Scv = scv; L->Tcu = tcu; L->Tcv = tcv;
         L->abp = abp; L->bbp = bbp; L->ps = (int16_t*)ps;
-        L->dg = (int32_t*)(d + a_off);
     }
     return off;
 }
@@ -337,7 +354,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
     const int C = Rw;                             // columns s = w + G c of this workgroup (same count)
     const uint32_t m = (uint32_t)((int64_t)n * (n - 1) / 2);
     Lds L_;
-    dist_layout(n, G, q, (int)sizeof(E), SYM, smem, &L_);
+    dist_layout(n, G, q, (int)sizeof(E), SYM, SCR, smem, &L_);
     // the LDS arrays as plain pointer values
     int32_t* const lD = L_.D;
     E* const lAb = (E*)L_.Ab;
@@ -379,24 +396,24 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
 
     // ---------------------------------------------------------------- load
     // A call with nothing to do (failed chain, or t already at t_end) leaves
-    // everything as it is.  Scratch mode (forced, or the chain's state says
-    // Delta is not being kept and Delta mode is not forced) needs no Delta: the LDS of the
-    // Delta rows holds the general form's own rows and columns of A instead,
-    // when they fit there.
+    // everything as it is.  The scratch-mode instantiation runs when scratch
+    // mode is forced, or when the chain's state says Delta is not being kept
+    // and Delta mode is not forced; it keeps no Delta and holds its own rows
+    // and columns of A in LDS (the general form).
     const qap_chain_state st0 = *a.state;
     if (st0.status != QAP_OK || st0.t >= a.t_end) return;
     const bool scr = SCR && ((a.flags & kFlagDeltaOnly) ? false : (a.flags & kFlagScratchOnly) ? true
                                                                                              : st0.mode != QAP_MODE_DELTA);
     if (SCR && !scr) return;
-    const bool a_lds = !SYM && scr && 2 * (size_t)P * sizeof(E) <= 4 * (size_t)n;
-    E* const lAr = (E*)lD;                        // [R][P] own rows of A - a_min (general form, scratch mode)
-    E* const lAc = lAr + (size_t)Rmax * P;        // [R][P] own columns of A - a_min
+    constexpr bool a_lds = !SYM && SCR;           // scratch mode: own rows and columns of A in LDS
+    E* const lAr = (E*)L_.Ar;                     // [R][P] own rows of A - a_min (general form, scratch mode)
+    E* const lAc = (E*)L_.Ac;                     // [R][P] own columns of A - a_min
     if (tid == 0) { s_ok = 1; s_rf_bad = 0; s_ntie[0] = 0; s_ntie[1] = 0; }
     __syncthreads();
     for (int lr = 0; lr < Rw; ++lr) {
         const int r = w + G * lr;
         const int32_t* up = a.delta + rs32(n, r) - r - 1;   // row r, s > r
-        if (!scr)
+        if constexpr (!SCR)
             for (int s = tid; s < n; s += nt) {
                 int d = 0;
                 if (s > r) d = up[s];
@@ -415,18 +432,19 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             if constexpr (SYM) lAb[lr * P + k] = (E)av;
             lBb[lr * P + k] = (E)bv;
             if constexpr (!SYM) lBt[lr * P + k] = (E)cv;
-            if (a_lds) { lAr[lr * P + k] = (E)av; lAc[lr * P + k] = (E)ac; }
+            if constexpr (a_lds) { lAr[lr * P + k] = (E)av; lAc[lr * P + k] = (E)ac; }
         }
     }
-    for (int k = tid; k < P; k += nt) {
-        lSu[k] = 0; lSv[k] = 0; lTu[k] = 0; lTv[k] = 0;
-        if constexpr (!SYM) { lScu[k] = 0; lScv[k] = 0; lTcu[k] = 0; lTcv[k] = 0; }
-    }
+    if constexpr (!SCR)
+        for (int k = tid; k < P; k += nt) {
+            lSu[k] = 0; lSv[k] = 0; lTu[k] = 0; lTv[k] = 0;
+            if constexpr (!SYM) { lScu[k] = 0; lScv[k] = 0; lTcu[k] = 0; lTcv[k] = 0; }
+        }
     for (int i = tid; i < n; i += nt) {
         const int pi = a.p[i];
         if (pi < 0 || pi >= n) s_ok = 0;   // p indexes B below
         lps[i] = (int16_t)pi;
-        if (scr) { L_.dg[i] = a.A[i * n + i]; L_.dg[n + i] = a.B[i * n + i]; }
+        if constexpr (SCR) { L_.dg[i] = a.A[i * n + i]; L_.dg[n + i] = a.B[i * n + i]; }
     }
     __syncthreads();
     if (!s_ok || (!scr && st0.mode == QAP_MODE_SCRATCH_STALE)) {
@@ -668,7 +686,14 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
             // needed by proposals (r, s) with r not that row; a candidate (r0, v)
             // with v owned here has row r0 read ahead
             bool spec = false, need_pend = pend >= 0 && rnd;
-            if (!rnd) {
+            if (!rnd && s0 + (int)W <= n) {
+                // the usual case: (r0, s0), ..., (r0, s0 + W - 1), owners of s0, s0 + 1, ... in turn
+                const int s0_own = uni(s0 % G);
+                int lag = w - s0_own;
+                if (lag < 0) lag += G;
+                spec = (uint32_t)lag < W;
+                need_pend = pend >= 0 && pend != r0;
+            } else if (!rnd) {
                 int rr = r0, ss = s0;
                 for (uint32_t jj = 0; jj < W; ++jj) {
                     if (jj) advance_pair(n, rr, ss, 1);
@@ -1390,11 +1415,17 @@ __global__ void k_dist_copies(int n, int P, const int32_t* __restrict__ A, const
 }
 
 template <typename E>
-int launch_dist_typed(DistArgs& a, bool symmetric, int G, int threads, size_t bytes, hipStream_t stream)
+int launch_dist_typed(DistArgs& a, bool symmetric, int G, int Gs, int threads, size_t bytes, size_t bytes_s,
+                      hipStream_t stream)
 {
     const void* fn_s = symmetric ? (const void*)k_chain_dist<true, E, true> : (const void*)k_chain_dist<false, E, true>;
     const void* fn_d = symmetric ? (const void*)k_chain_dist<true, E, false> : (const void*)k_chain_dist<false, E, false>;
-    if (hipFuncSetAttribute(fn_s, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess ||
+    // the static __shared__ variables come on top of the dynamic layout
+    hipFuncAttributes fa_s, fa_d;
+    if (hipFuncGetAttributes(&fa_s, fn_s) != hipSuccess || hipFuncGetAttributes(&fa_d, fn_d) != hipSuccess)
+        return QAP_E_DEVICE;
+    if (fa_s.sharedSizeBytes + bytes_s > kLdsLimit || fa_d.sharedSizeBytes + bytes > kLdsLimit) return QAP_E_UNSUPPORTED;
+    if (hipFuncSetAttribute(fn_s, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes_s) != hipSuccess ||
         hipFuncSetAttribute(fn_d, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
         return QAP_E_DEVICE;
     if (!symmetric) {   // the copies precede the run on the same stream
@@ -1405,12 +1436,12 @@ int launch_dist_typed(DistArgs& a, bool symmetric, int G, int threads, size_t by
         hipLaunchKernelGGL(k_dist_copies<E>, dim3(blocks), dim3(256), 0, stream, a.n, P, a.A, a.B, a.a_min, a.b_min,
                            (E*)a.Ab, (E*)a.Atb, (E*)a.Btb);
     }
-    const int Rmax = (a.n + G - 1) / G;
-    auto run = [&](const void* fn) -> int {
-        hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, stream, a.ws, a.slots, a.X, 2 * 2 * G * Rmax, a.Pp,
-                           scratch_reps(G) * G * kScratchK);
+    auto run = [&](const void* fn, int g, size_t b) -> int {
+        const int rmax = (a.n + g - 1) / g;
+        hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, stream, a.ws, a.slots, a.X, 2 * 2 * g * rmax, a.Pp,
+                           scratch_reps(g) * g * kScratchK);
         void* kargs[] = {&a};
-        if (hipLaunchCooperativeKernel(fn, dim3(G), dim3(threads), kargs, (unsigned)bytes, stream) != hipSuccess)
+        if (hipLaunchCooperativeKernel(fn, dim3(g), dim3(threads), kargs, (unsigned)b, stream) != hipSuccess)
             return QAP_E_DEVICE;
         return QAP_OK;
     };
@@ -1421,9 +1452,9 @@ int launch_dist_typed(DistArgs& a, bool symmetric, int G, int threads, size_t by
     // the rebuild and the second launch read the chain state on the device
     // and do nothing when there is nothing to do.
     int rc = QAP_OK;
-    if (!(a.flags & kFlagDeltaOnly)) rc = run(fn_s);
+    if (!(a.flags & kFlagDeltaOnly)) rc = run(fn_s, Gs, bytes_s);
     if (rc == QAP_OK) rc = launch_delta_rebuild(a.n, a.A, a.Bp, a.delta, a.state, a.t_end, a.iters, stream);
-    if (rc == QAP_OK && !(a.flags & kFlagScratchOnly)) rc = run(fn_d);
+    if (rc == QAP_OK && !(a.flags & kFlagScratchOnly)) rc = run(fn_d, G, bytes);
     return rc;
 }
 
@@ -1431,23 +1462,40 @@ int launch_dist_typed(DistArgs& a, bool symmetric, int G, int threads, size_t by
 
 int dist_words(int n, int esize) { return (int)(((size_t)n * esize + 3) / 4); }
 
-size_t lds_dist_bytes(int n, int G, bool symmetric, int esize)
+size_t lds_dist_bytes(int n, int G, bool symmetric, int esize, bool scratch)
 {
-    return dist_layout(n, G, dist_words(n, esize), esize, symmetric, nullptr, nullptr);
+    return dist_layout(n, G, dist_words(n, esize), esize, symmetric, scratch, nullptr, nullptr);
+}
+
+constexpr int kScratchRows = 16;   // own rows per workgroup sought for scratch-mode launches
+
+// Workgroups of a scratch-mode launch: about kScratchRows own rows each
+// where the LDS allows (N = 2000: 125 workgroups, against 250 for Delta
+// mode), never more than the Delta-mode launch's G.  Measured at N = 2000
+// over the first 1e6 iterations: 16 rows 2.49 s symmetric and 2.73 s
+// asymmetric, 8 rows 2.56 and 2.75, 32 rows 2.56 and 2.82.
+int dist_scratch_groups(int n, int G, bool symmetric, int esize, size_t budget)
+{
+    int gs = (n + kScratchRows - 1) / kScratchRows;
+    if (gs < 2) gs = 2;
+    while (gs < G && lds_dist_bytes(n, gs, symmetric, esize, true) > budget) ++gs;
+    return gs < G ? gs : G;
 }
 
 int launch_chain_dist(const DistArgs& a0, bool symmetric, int esize, int G, int threads, hipStream_t stream)
 {
     DistArgs a = a0;
     a.quads = dist_words(a.n, esize);
-    const size_t bytes = lds_dist_bytes(a.n, G, symmetric, esize);
+    const size_t bytes = lds_dist_bytes(a.n, G, symmetric, esize, false);
+    const int Gs = dist_scratch_groups(a.n, G, symmetric, esize, kLdsLimit - kDistStaticReserve);
+    const size_t bytes_s = lds_dist_bytes(a.n, Gs, symmetric, esize, true);
     if (G > kMaxGroups || threads > 512 || threads % 64 != 0 || a.n > kMaxPerThread * threads ||
         (a.n + G - 1) / G > kMaxOwnRows)
         return QAP_E_INVAL;
     switch (esize) {
-    case 1: return launch_dist_typed<uint8_t>(a, symmetric, G, threads, bytes, stream);
-    case 2: return launch_dist_typed<uint16_t>(a, symmetric, G, threads, bytes, stream);
-    case 4: return launch_dist_typed<uint32_t>(a, symmetric, G, threads, bytes, stream);
+    case 1: return launch_dist_typed<uint8_t>(a, symmetric, G, Gs, threads, bytes, bytes_s, stream);
+    case 2: return launch_dist_typed<uint16_t>(a, symmetric, G, Gs, threads, bytes, bytes_s, stream);
+    case 4: return launch_dist_typed<uint32_t>(a, symmetric, G, Gs, threads, bytes, bytes_s, stream);
     default: return QAP_E_INVAL;
     }
 }

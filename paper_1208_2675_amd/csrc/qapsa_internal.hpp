@@ -52,6 +52,7 @@ struct ChainArgs {
 size_t lds_chain_bytes(int n, bool symmetric, bool a_in_lds);
 constexpr size_t kLdsLimit = 160 * 1024;
 constexpr size_t kLdsStaticReserve = 2048;  // the kernels' static __shared__ variables
+constexpr size_t kDistStaticReserve = 4096; // the multi-workgroup kernel's (about 2.6 KB)
 
 int launch_cost(int n, const int32_t* A, const int32_t* B, const int32_t* p, int64_t* cost,
                 hipStream_t stream);
@@ -161,7 +162,8 @@ inline int dist_esize(int64_t a_range, int64_t b_range)
     return r <= 255 ? 1 : (r <= 65535 ? 2 : 4);
 }
 int dist_words(int n, int esize);
-size_t lds_dist_bytes(int n, int G, bool symmetric, int esize);
+size_t lds_dist_bytes(int n, int G, bool symmetric, int esize, bool scratch = false);
+int dist_scratch_groups(int n, int G, bool symmetric, int esize, size_t budget);
 int launch_chain_dist(const DistArgs& a, bool symmetric, int esize, int G, int threads, hipStream_t stream);
 
 // batched chains (one persistent launch, a device-wide work queue)
