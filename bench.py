@@ -30,6 +30,11 @@ Further sections, reported in the same JSON line:
   tabu     tabu search on the single-chain instance (tenure N): iterations/s
            (one swap each), the first iterations checked against the oracle's
            tabu search.
+  prefix   (not in the default set) the first --prefix-iters iterations of a
+           single-chain workload (--prefix-workload) with chain flags
+           --prefix-flags (default 2, scratch mode only), one call: seconds,
+           iterations/s and scratch rounds (the run that SQ counters are
+           taken on).
   config2  (not in the default set) the N = 2000 symmetric chain over its whole
            schedule of 1e9 iterations in slices of 1e7, resumable across calls
            through a state file: iterations/s, Delta-updates/s and acceptance
@@ -514,6 +519,27 @@ def section_serve(Q, W, torch, args, jobs=None):
     return out
 
 
+def section_prefix(Q, W, torch, args):
+    """A prefix of one single-chain run with the given flags, one call; the
+    phase counters come from a second, identical run (they cost a little)."""
+    ch = W.single_chain(args.prefix_workload)
+    t_end = min(args.prefix_iters, ch.iters)
+    log(f"prefix: workload={args.prefix_workload} n={ch.n} t_end={t_end} flags={args.prefix_flags}")
+    c = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id, flags=args.prefix_flags).init()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.run(t_end)
+    st = c.state()
+    dt = time.perf_counter() - t0
+    cp = Q.Chain(ch.A, ch.B, ch.p0, ch.iters, ch.philox_seed, ch.chain_id, flags=args.prefix_flags,
+                 profile=True).init()
+    cp.run(t_end)
+    ph = cp.phases()
+    return {"workload": args.prefix_workload, "n": ch.n, "t_end": t_end, "flags": args.prefix_flags, "s": dt,
+            "iterations_per_s": t_end / dt, "accepts": int(st.accepts), "hash": int(st.hash),
+            "status": int(st.status), "phase_cycles": ph}
+
+
 def section_config2(Q, W, torch, args):
     """The N = 2000 symmetric chain over its whole schedule (I = 1e9) in
     slices of args.c2_slice iterations, as many as fit args.c2_budget seconds
@@ -673,6 +699,9 @@ def main():
     ap.add_argument("--c2-state", default="gpurun_out/config2_state.npz", help="state file written after each slice")
     ap.add_argument("--c2-resume", default=None, help="state file of an earlier call to continue from")
     ap.add_argument("--c2-slice", type=int, default=10_000_000)
+    ap.add_argument("--prefix-workload", default="n150_asym")
+    ap.add_argument("--prefix-iters", type=int, default=2_000_000)
+    ap.add_argument("--prefix-flags", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -703,6 +732,8 @@ def main():
             line["random_order"] = section_random(Q, W, torch, args, res)
         if "tabu" in sections:
             line["tabu"] = section_tabu(Q, W, torch, args, res)
+        if "prefix" in sections:
+            line["prefix"] = section_prefix(Q, W, torch, args)
         if "config2" in sections:
             line["config2"] = section_config2(Q, W, torch, args)
         print(json.dumps(line))
