@@ -299,13 +299,17 @@ def section_single(Q, W, torch, args, cpu_jobs=None):
         st = c.state()                # syncs
         return st, ev0.elapsed_time(ev1)
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step()
+        log(f"single: warm-up step {i + 1}/{args.warmup}")
     torch.cuda.synchronize()
     if cpu_jobs is not None:   # the CPU baselines ran during the warm-up; the timed steps run alone
         cpu_jobs.join()
     t0 = time.perf_counter()
-    results = [step() for _ in range(args.steps)]
+    results = []
+    for i in range(args.steps):
+        results.append(step())
+        log(f"single: step {i + 1}/{args.steps}: {results[-1][1] / 1e3:.3f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = results[-1][0]
