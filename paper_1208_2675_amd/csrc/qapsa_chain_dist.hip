@@ -639,16 +639,17 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
         // copy w mod reps: fewer readers per line (7% faster at N = 2000 with
         // four copies than with one)
         const int reps = scratch_reps(G);
-        // Rows of B' read ahead, so that a swap does not wait for them: the
-        // owner of the v of a candidate (r0, v) reads row (and column) r0,
-        // which becomes row v when (r0, v) is accepted (two entries change
-        // places); the owner of u of an accepted swap reads its new row u and
-        // writes it in the next window, before the row is first needed.  One
-        // element of each of this thread's columns k = tid + i * nt.
+        // Rows of B' read off the critical path, after this workgroup's
+        // partial sums are out and while the exchange runs: the owner of the
+        // v of a candidate (r0, v) reads row (and column) r0, which becomes
+        // row v when (r0, v) is accepted (two entries change places); the
+        // owner of u of an accepted swap reads its new row u in the next
+        // window (before its partial sums only when a proposal needs the row).
+        // One element of each of this thread's columns k = tid + i * nt.
         uint32_t sp_row[kMaxPerThread], sp_col[kMaxPerThread];
         uint32_t pd_row[kMaxPerThread], pd_col[kMaxPerThread];
         int spec_r = -1;    // row read ahead into sp_*, or -1
-        int pend = -1;      // own row whose new content waits in pd_*, or -1
+        int pend = -1;      // own row to be read again through p (after a swap), or -1
         // row x of B' (and column x, general form) from registers; the
         // entries at ua and va change places (none when ua < 0)
         auto write_row = [&](int x, const uint32_t* vr, const uint32_t* vc, int ua, int va)
@@ -702,11 +703,11 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 }
             }
             if (need_pend) {
+                read_row((int)lps[pend], -1, -1, 0, 0, pd_row, pd_col);
                 write_row(pend, pd_row, pd_col, -1, -1);
                 pend = -1;
                 __syncthreads();
             }
-            if (spec) read_row((int)lps[r0], -1, -1, 0, 0, sp_row, sp_col);   // old row r0, current p
             spec_r = spec ? r0 : -1;
             // wave 0: this workgroup's partial sums, one proposal per lane j < K
             // (lanes j, j + K, ... split the own rows).  The owner of row s
@@ -755,8 +756,11 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 // log r_t of Eq. (2) while the exchange runs
                 if ((uint32_t)j < W && !t0_inf) ylog = log(uniform_r(seed, chain_id, t + (uint64_t)j));
             }
-            // the pending row, not read by this window's partials, lands now
+            // rows read now: the old row r0 for a candidate's v (current p), and
+            // the pending row (not read by this window's partial sums)
+            if (spec) read_row((int)lps[r0], -1, -1, 0, 0, sp_row, sp_col);
             if (pend >= 0) {
+                read_row((int)lps[pend], -1, -1, 0, 0, pd_row, pd_col);
                 write_row(pend, pd_row, pd_col, -1, -1);
                 pend = -1;
             }
@@ -872,9 +876,9 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                     }
                 }
                 // own row v: the row read ahead (old row u, entries u and v
-                // exchanged) when it is this window's, else read now; own row
-                // u: read now, written in the next window.  Neither reads p at
-                // u or v, which thread 0 changes meanwhile.
+                // exchanged) when it is this window's, else read now (not
+                // reading p at u or v, which thread 0 changes meanwhile); own
+                // row u: read in the next window, through the new p
                 if (v % G == w) {
                     if (spec_r == u) {
                         write_row(v, sp_row, sp_col, u, v);
@@ -883,10 +887,7 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                         write_row(v, sp_row, sp_col, -1, -1);
                     }
                 }
-                if (u % G == w) {
-                    read_row(pu_new, u, v, pu_new, pv_new, pd_row, pd_col);
-                    pend = u;
-                }
+                if (u % G == w) pend = u;
                 if (tid == 0) { lps[u] = (int16_t)pu_new; lps[v] = (int16_t)pv_new; }
                 t = tstar + 1;
                 win_iters += jstar + 1;
@@ -910,7 +911,11 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                 win_iters = win_acc = 0;
             }
         }
-        if (pend >= 0) write_row(pend, pd_row, pd_col, -1, -1);
+        if (pend >= 0) {
+            __syncthreads();   // thread 0's last write of p is visible
+            read_row((int)lps[pend], -1, -1, 0, 0, pd_row, pd_col);
+            write_row(pend, pd_row, pd_col, -1, -1);
+        }
         // write back: B' rows, p and the state; Delta is left stale
         __syncthreads();
         if (w == 0 && nrec > 0) flush();
