@@ -312,12 +312,16 @@ struct Chain {
     }
 
     // This lane's share of the all-k dot sums of the pair (r, s) (wave-uniform
-    // r != s) for the current B'.
-    __device__ __forceinline__ int lane_part(int r, int s) const
+    // r != s) for the current B': <A_r - A_s, B'_s - B'_rb> over rows (and the
+    // same over columns), with rb = r.  With rb = y, the same sums for the
+    // state after the swap (r, y), up to the two entries x = r, y that the
+    // swap exchanges (see finish_after).
+    __device__ __forceinline__ int lane_part(int r, int s, int rb = -1) const
     {
-        const uint32_t *ar = row(L.Ab, r), *as = row(L.Ab, s), *br = row(L.Bb, r), *bs = row(L.Bb, s);
+        if (rb < 0) rb = r;
+        const uint32_t *ar = row(L.Ab, r), *as = row(L.Ab, s), *br = row(L.Bb, rb), *bs = row(L.Bb, s);
         const uint32_t *cr = nullptr, *cs = nullptr, *dr = nullptr, *ds = nullptr;
-        if constexpr (!SYM) { cr = row(L.At, r); cs = row(L.At, s); dr = row(L.Bt, r); ds = row(L.Bt, s); }
+        if constexpr (!SYM) { cr = row(L.At, r); cs = row(L.At, s); dr = row(L.Bt, rb); ds = row(L.Bt, s); }
         uint32_t pos = 0, neg = 0;
         for (int k = lane; k < q; k += 64) {
             const uint32_t xr = ar[k], xs = as[k], yr = br[k], ys = bs[k];
@@ -336,6 +340,26 @@ struct Chain {
     __device__ __forceinline__ int finish_pair(int S, int r, int s) const
     {
         return finish_delta<SYM>(S, Ae(r, r), Ae(r, s), Ae(s, r), Ae(s, s), Be(r, r), Be(r, s), Be(s, r), Be(s, s));
+    }
+
+    // Swap cost of the pair (r, s) in the state after the swap (r, y) (s not
+    // in {r, y}), from S = lane sums of lane_part(r, s, y).  The swap permutes
+    // rows and columns of B' by sigma = (r y): B''[i][j] = B'[sigma(i)][sigma(j)],
+    // so row s of B'' minus row r is (B'_s - B'_y) with entries r, y exchanged,
+    // and <g, f o sigma> = <g, f> + (g_r - g_y)(f_y - f_r) (the same for
+    // columns); then the k in {r, s} terms and the corner, with B'' entries.
+    __device__ __forceinline__ int finish_after(int S, int r, int s, int y) const
+    {
+        const int gx = Ae(r, r) - Ae(s, r), gy = Ae(r, y) - Ae(s, y);
+        const int fx = Be(s, r) - Be(y, r), fy = Be(s, y) - Be(y, y);
+        int Sc = S + (gx - gy) * (fy - fx);
+        if constexpr (!SYM) {   // columns: g = A[.][r] - A[.][s], f = B'[.][s] - B'[.][y]
+            const int hx = Ae(r, r) - Ae(r, s), hy = Ae(y, r) - Ae(y, s);
+            const int ex = Be(r, s) - Be(r, y), ey = Be(y, s) - Be(y, y);
+            Sc += (hx - hy) * (ey - ex);
+        }
+        // B'' at (r,r), (r,s), (s,r), (s,s): B' at (y,y), (y,s), (s,y), (s,s)
+        return finish_delta<SYM>(Sc, Ae(r, r), Ae(r, s), Ae(s, r), Ae(s, s), Be(y, y), Be(y, s), Be(s, y), Be(s, s));
     }
 
     // This wave's share of the swap (u, v) applied to B' (and B'^T): rows u
@@ -543,6 +567,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
     // from an LDS copy where they are used and the running statistics are
     // kept by thread 0 alone.
     __shared__ unsigned long long s_wkey[2][kWaves];   // per-wave first acceptance (j << 32 | Delta), by round parity
+    __shared__ unsigned long long s_akey[2][kWaves];   // the same for the proposals after the window's first (see scratch_round_ahead)
     __shared__ unsigned long long s_ties;
     __shared__ int s_flag;
     __shared__ unsigned long long s_prof[QAP_PHASES];
@@ -833,6 +858,93 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         }
     };
 
+    // A scratch round of four proposals (r0, s0 + w), one per wave w, that
+    // also tests the four proposals that follow the first one, (r0, s0 + 1 + w),
+    // in the state after the swap (r0, s0): when that first proposal is
+    // accepted (about half the rounds while half the proposals are), the round
+    // goes on to the first acceptance among them, and one round makes two
+    // swaps.  Wave w sums both dot products together (lane_part with row s0 of
+    // B' in place of row r0 gives the sums after the swap up to two exchanged
+    // entries, which finish_after corrects).  For rounds inside one row of the
+    // cyclic order (s0 + 4 < n), in row-major order, with all five iterations
+    // in the slice.
+    auto scratch_round_ahead = [&]() __attribute__((always_inline)) {
+        constexpr int K = kWaves;
+        if (tau_base == ~0ull || t + K + 1 > tau_base + ring_len) refill();
+        const int r = r0, sn = uni(s0 + wave), sa = uni(s0 + 1 + wave);
+        int Sn, Sa;
+        {
+            const int pn = C.lane_part(r, sn), pa = C.lane_part(r, sa, s0);
+            const int z = row_sums(half_fold(pn, pa));
+            Sn = __builtin_amdgcn_readlane(z, 15) + __builtin_amdgcn_readlane(z, 31);
+            Sa = __builtin_amdgcn_readlane(z, 47) + __builtin_amdgcn_readlane(z, 63);
+        }
+        // lane 0: the window's proposal at t + w; lane 1: the one after the swap, at t + 1 + w
+        const int dn = C.finish_pair(Sn, r, sn), da = C.finish_after(Sa, r, sa, s0);
+        const bool after = lane == 1;
+        const int dl = after ? da : dn;
+        const uint32_t jo = (uint32_t)wave + (after ? 1u : 0u);
+        const bool valid = lane < 2;
+        const int32_t tau = L.tau[(uint32_t)(t - tau_base) + jo];
+        bool acc = valid && dl <= tau;
+        bool tie = false;
+        double zt = 0.0;
+        if (valid && dl > 0 && (ring_exact || (dl >= tau - 1 && dl <= tau + 2)) &&
+            !(t0_inf && inf_draw_clear(seed, chain_id, t + jo))) {
+            const bool ex = exact_test(dl, temps, T0, seed, chain_id, t + jo, &zt);
+            if (ring_exact) acc = ex;
+            tie = fabs(zt) < kNearTie;
+        }
+        const unsigned long long mask = __ballot(acc);
+        if (lane == 0) {
+            s_wkey[buf][wave] = (mask & 1ull) ? (((unsigned long long)wave << 32) | (uint32_t)dn) : ~0ull;
+            s_akey[buf][wave] = (mask & 2ull) ? (((unsigned long long)wave << 32) | (uint32_t)da) : ~0ull;
+        }
+        __syncthreads();
+        unsigned long long akey = s_akey[buf][0];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) {
+            const unsigned long long x = s_akey[buf][w];
+            akey = x < akey ? x : akey;
+        }
+        akey = uni64(akey);
+        const unsigned long long key = min_key();   // flips buf
+        const int jstar = key == ~0ull ? -1 : (int)(key >> 32);
+        const int istar = (jstar != 0 || akey == ~0ull) ? -1 : (int)(akey >> 32);
+        mark(QAP_PH_SCRATCH_EVAL);
+        bump(QAP_PH_N_ROUNDS, 1);
+        // near ties a sequential run meets: the window's proposals up to the
+        // first acceptance, and those after the swap when it is the first one
+        if (tie && !after && (jstar < 0 || wave <= jstar)) log_tie(t + jo, dl, zt);
+        if (tie && after && jstar == 0 && (istar < 0 || wave <= istar)) log_tie(t + jo, dl, zt);
+        if (jstar < 0) {
+            advance(K);
+            win_iters += K;
+            return;
+        }
+        accept_common(t + jstar, r, s0 + jstar, (int)(uint32_t)key);
+        __syncthreads();
+        if (nrec == kRec) flush();
+        uint32_t used = (uint32_t)jstar + 1;
+        win_acc += 1;
+        if (jstar == 0) {
+            if (istar >= 0) {
+                accept_common(t + 1 + istar, r, s0 + 1 + istar, (int)(uint32_t)akey);
+                __syncthreads();
+                if (nrec == kRec) flush();
+                used = (uint32_t)istar + 2;
+                win_acc += 1;
+                bump(QAP_PH_N_SCRATCH_ACC, 1);
+            } else {
+                used = K + 1;   // the four proposals after the swap were all rejected
+            }
+        }
+        advance(used);
+        win_iters += used;
+        mark(QAP_PH_SCRATCH_ACCEPT);
+        bump(QAP_PH_N_SCRATCH_ACC, 1);
+    };
+
     // One Delta-mode step: scan up to step_e proposals per thread against the
     // unchanged Delta; on an acceptance, swap and update Delta.
     auto delta_step = [&]() __attribute__((always_inline)) {
@@ -1011,9 +1123,14 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
     } else
     while (t < t_end) {
         if (mode == 0) {
-            if (kw == 1) scratch_round(IC<1>{});
-            else if (kw == 2) scratch_round(IC<2>{});
-            else scratch_round(IC<4>{});
+            if (kw == 1) {
+                if (!rnd && s0 + kWaves < n && t + kWaves + 1 <= t_end) scratch_round_ahead();
+                else scratch_round(IC<1>{});
+            } else if (kw == 2) {
+                scratch_round(IC<2>{});
+            } else {
+                scratch_round(IC<4>{});
+            }
             if (win_iters >= kSwitchWindow) {
                 // few proposals per round while most are accepted, more as acceptance
                 // falls: 1 per wave above 1/4, 2 above 1/8, else 4 (the cut points
