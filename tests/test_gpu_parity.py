@@ -142,6 +142,32 @@ def test_chain_infinite_temperature(orc, Q, flags):
     assert got["accepts"] == 5000
 
 
+@pytest.mark.parametrize("n,sym", [(40, False), (41, True), (6, False)])
+def test_lookahead_rounds_make_two_swaps(orc, Q, n, sym):
+    """Scratch rounds that also test the proposals after the window's first
+    one: at T = +inf every proposal is accepted, so nearly every round makes two
+    swaps (its first proposal and the next one, in the state after the first
+    swap), except at the ends of rows of the cyclic order, where plain rounds
+    run; the run equals the oracle's swap by swap."""
+    A, B, p0 = _inst(n, 80 + n, sym)
+    iters = 3000
+    sched = orc.schedule(A, B, p0, iters)
+    ref = orc.sa_run(A, B, p0, iters, math.inf, sched["alpha"], 4, 0, acc_cap=iters, tie_cap=16)
+    ch = Q.Chain(A, B, p0, iters, 4, 0, T0=math.inf, accept_cap=iters, flags=Q.QAP_FLAG_SCRATCH_ONLY,
+                 profile=True).init()
+    ch.run(1234)
+    ch.run()
+    got = ch.result(with_delta=True)
+    for k in ("t", "accepts", "hash", "cost", "best_cost", "best_iter"):
+        assert got[k] == ref[k], (k, got[k], ref[k])
+    assert np.array_equal(got["accept_log"], ref["accept_log"])
+    assert np.array_equal(got["Bp"], B[np.ix_(got["p"], got["p"])])
+    ph = ch.phases()
+    assert ph["n_scratch_acc"] == iters
+    if n >= 40:   # rows of the cyclic order long enough for the look-ahead to run in most rounds
+        assert ph["n_rounds"] < 0.7 * iters, ph["n_rounds"]
+
+
 def test_chain_near_zero_temperature(orc, Q):
     A, B, p0 = _inst(25, 78, True)
     _compare_run(orc, Q, A, B, p0, 20000, seed=9, T0=1e-300)
