@@ -255,28 +255,31 @@ __device__ __forceinline__ void advance_by(int n, int& r, int& s, int k)
 
 // Eq. (2) for Delta > 0 at iteration t, out of line: it is the rare path of
 // the scratch rounds and of the scan, and inlined copies of the FP64 log and
-// the generator cost scalar registers everywhere else.
-__device__ __noinline__ bool exact_test(int d, const double* temps, double T0, uint64_t seed, uint32_t chain,
-                                        uint64_t t, double* z)
+// the generator cost scalar registers everywhere else.  Returns
+// z = fl(Delta / T_t + log r_t); the swap is accepted iff z < 0.  (A value, not
+// a pointer argument, so that callers keep no stack slot.)
+__device__ __noinline__ double exact_z(int d, const double* temps, double T0, uint64_t seed, uint32_t chain,
+                                       uint64_t t)
 {
-    return metropolis_positive(d, temperature(temps, T0, t), uniform_r(seed, chain, t), z);
+    double z;
+    metropolis_positive(d, temperature(temps, T0, t), uniform_r(seed, chain, t), &z);
+    return z;
 }
 
 // Acceptance threshold of iteration t: the largest Delta that Eq. (2) accepts
-// (Eq. (2) is monotone in Delta).  *exact is set when T_t is so large that
+// (Eq. (2) is monotone in Delta), in .x; .y is set when T_t is so large that
 // near ties cannot be located from the threshold alone.
-__device__ __noinline__ int32_t threshold_at(const double* temps, double T0, uint64_t seed, uint32_t chain,
-                                             uint64_t t, bool* exact)
+__device__ __noinline__ int2 threshold_at(const double* temps, double T0, uint64_t seed, uint32_t chain,
+                                          uint64_t t)
 {
     const double T = temperature(temps, T0, t);
     const double y = log(uniform_r(seed, chain, t));
-    if (!(T <= 1e9)) *exact = true;
     const double xs = -y * T;
     int64_t d = xs >= 2147483647.0 ? 2147483647 : (int64_t)xs;
     auto acc = [&](int64_t dd) { return dd <= 0 || ((double)dd / T + y) < 0.0; };
     while (d < 2147483647 && acc(d + 1)) ++d;
     while (d > 0 && !acc(d)) --d;
-    return (int32_t)d;
+    return make_int2((int32_t)d, !(T <= 1e9) ? 1 : 0);
 }
 
 template <bool SYM, int PL>
@@ -319,21 +322,53 @@ struct Chain {
     __device__ __forceinline__ int lane_part(int r, int s, int rb = -1) const
     {
         if (rb < 0) rb = r;
-        const uint32_t *ar = row(L.Ab, r), *as = row(L.Ab, s), *br = row(L.Bb, rb), *bs = row(L.Bb, s);
-        const uint32_t *cr = nullptr, *cs = nullptr, *dr = nullptr, *ds = nullptr;
-        if constexpr (!SYM) { cr = row(L.At, r); cs = row(L.At, s); dr = row(L.Bt, rb); ds = row(L.Bt, s); }
-        uint32_t pos = 0, neg = 0;
-        for (int k = lane; k < q; k += 64) {
-            const uint32_t xr = ar[k], xs = as[k], yr = br[k], ys = bs[k];
-            pos = dot4(xr, ys, pos); pos = dot4(xs, yr, pos);
-            neg = dot4(xr, yr, neg); neg = dot4(xs, ys, neg);
-            if constexpr (!SYM) {
-                const uint32_t zr = cr[k], zs = cs[k], wr = dr[k], ws = ds[k];
-                pos = dot4(zr, ws, pos); pos = dot4(zs, wr, pos);
-                neg = dot4(zr, wr, neg); neg = dot4(zs, ws, neg);
+        int out[1];
+        const int rr[1] = {r}, ss[1] = {s}, bb[1] = {rb};
+        lane_parts<1>(rr, ss, bb, out);
+        return out[0];
+    }
+
+    // lane_part of NP pairs (r[i], s[i]) with rows rb[i] of B', in one pass
+    // over k: every LDS read of the pass is issued before the first product.
+    // For q <= 64 (n <= 256) each lane takes one k, clamped to q - 1 so that
+    // every read stays inside its row, and lanes past q contribute nothing.
+    template <int NP>
+    __device__ __forceinline__ void lane_parts(const int (&r)[NP], const int (&s)[NP], const int (&rb)[NP],
+                                               int (&out)[NP]) const
+    {
+        uint32_t pos[NP], neg[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) pos[i] = neg[i] = 0;
+        auto body = [&](int k) __attribute__((always_inline)) {
+            uint32_t xr[NP], xs[NP], yr[NP], ys[NP], zr[NP], zs[NP], wr[NP], ws[NP];
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                xr[i] = row(L.Ab, r[i])[k]; xs[i] = row(L.Ab, s[i])[k];
+                yr[i] = row(L.Bb, rb[i])[k]; ys[i] = row(L.Bb, s[i])[k];
+                if constexpr (!SYM) {
+                    zr[i] = row(L.At, r[i])[k]; zs[i] = row(L.At, s[i])[k];
+                    wr[i] = row(L.Bt, rb[i])[k]; ws[i] = row(L.Bt, s[i])[k];
+                }
             }
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                pos[i] = dot4(xr[i], ys[i], pos[i]); pos[i] = dot4(xs[i], yr[i], pos[i]);
+                neg[i] = dot4(xr[i], yr[i], neg[i]); neg[i] = dot4(xs[i], ys[i], neg[i]);
+                if constexpr (!SYM) {
+                    pos[i] = dot4(zr[i], ws[i], pos[i]); pos[i] = dot4(zs[i], wr[i], pos[i]);
+                    neg[i] = dot4(zr[i], wr[i], neg[i]); neg[i] = dot4(zs[i], ws[i], neg[i]);
+                }
+            }
+        };
+        if (q <= 64) {
+            body(min(lane, q - 1));
+#pragma unroll
+            for (int i = 0; i < NP; ++i) out[i] = lane < q ? (int)(pos[i] - neg[i]) : 0;
+        } else {
+            for (int k = lane; k < q; k += 64) body(k);
+#pragma unroll
+            for (int i = 0; i < NP; ++i) out[i] = (int)(pos[i] - neg[i]);
         }
-        return (int)(pos - neg);
     }
 
     // Swap cost of the pair (r, s) held by this lane, from its all-k sum S.
@@ -348,18 +383,45 @@ struct Chain {
     // so row s of B'' minus row r is (B'_s - B'_y) with entries r, y exchanged,
     // and <g, f o sigma> = <g, f> + (g_r - g_y)(f_y - f_r) (the same for
     // columns); then the k in {r, s} terms and the corner, with B'' entries.
+    // With y = r (no swap before) this is finish_pair.
     __device__ __forceinline__ int finish_after(int S, int r, int s, int y) const
     {
-        const int gx = Ae(r, r) - Ae(s, r), gy = Ae(r, y) - Ae(s, y);
-        const int fx = Be(s, r) - Be(y, r), fy = Be(s, y) - Be(y, y);
+        return fin_eval(S, fin_load(r, s, y));
+    }
+
+    // The entries of A and B' that finish_after(S, r, s, y) reads, loaded
+    // apart from the arithmetic so that a round can issue the reads before
+    // its dot products and find them there when the lane sums are in.
+    struct Fin {
+        int arr, ars, asr, ass, ary, asy, ayr, ays;   // A at (r,r), (r,s), (s,r), (s,s), (r,y), (s,y), (y,r), (y,s)
+        int bsr, byr, bsy, byy, bys, bss, brs, bry;   // B' at (s,r), (y,r), (s,y), (y,y), (y,s), (s,s), (r,s), (r,y)
+    };
+    __device__ __forceinline__ Fin fin_load(int r, int s, int y) const
+    {
+        Fin f;
+        f.arr = Ae(r, r); f.ars = Ae(r, s); f.asr = Ae(s, r); f.ass = Ae(s, s);
+        f.ary = Ae(r, y); f.asy = Ae(s, y);
+        f.bsr = Be(s, r); f.byr = Be(y, r); f.bsy = Be(s, y); f.byy = Be(y, y); f.bys = Be(y, s); f.bss = Be(s, s);
+        if constexpr (!SYM) {
+            f.ayr = Ae(y, r); f.ays = Ae(y, s);
+            f.brs = Be(r, s); f.bry = Be(r, y);
+        } else {
+            f.ayr = f.ays = f.brs = f.bry = 0;
+        }
+        return f;
+    }
+    __device__ __forceinline__ int fin_eval(int S, const Fin& f) const
+    {
+        const int gx = f.arr - f.asr, gy = f.ary - f.asy;
+        const int fx = f.bsr - f.byr, fy = f.bsy - f.byy;
         int Sc = S + (gx - gy) * (fy - fx);
         if constexpr (!SYM) {   // columns: g = A[.][r] - A[.][s], f = B'[.][s] - B'[.][y]
-            const int hx = Ae(r, r) - Ae(r, s), hy = Ae(y, r) - Ae(y, s);
-            const int ex = Be(r, s) - Be(r, y), ey = Be(y, s) - Be(y, y);
+            const int hx = f.arr - f.ars, hy = f.ayr - f.ays;
+            const int ex = f.brs - f.bry, ey = f.bys - f.byy;
             Sc += (hx - hy) * (ey - ex);
         }
         // B'' at (r,r), (r,s), (s,r), (s,s): B' at (y,y), (y,s), (s,y), (s,s)
-        return finish_delta<SYM>(Sc, Ae(r, r), Ae(r, s), Ae(s, r), Ae(s, s), Be(y, y), Be(y, s), Be(s, y), Be(s, s));
+        return finish_delta<SYM>(Sc, f.arr, f.ars, f.asr, f.ass, f.byy, f.bys, f.bsy, f.bss);
     }
 
     // This wave's share of the swap (u, v) applied to B' (and B'^T): rows u
@@ -745,7 +807,10 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         const uint64_t iters = a.iters;
         for (int i = tid; i < (int)ring_len; i += kThreads) {
             const uint64_t tt = tau_base + i;
-            L.tau[i] = tt < iters ? threshold_at(temps, T0, seed, chain_id, tt, &ex) : 0;
+            int2 th = make_int2(0, 0);
+            if (tt < iters) th = threshold_at(temps, T0, seed, chain_id, tt);
+            L.tau[i] = th.x;
+            ex |= th.y != 0;
             if (rnd) {
                 int r = 0, s = 1;
                 if (tt < iters) pair_of_u(n, random_pair_index(seed, chain_id, tt, m), r, s);
@@ -783,11 +848,19 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
                 if (i + 1 < KW) advance_by(n, r, s, 1);
             }
         }
+        // lane i < KW finishes proposal i of this wave: its entries of A and
+        // B' and its threshold are read first, the dot products after them
+        int my_r = pr[0], my_s = pc[0];
+#pragma unroll
+        for (int i = 1; i < KW; ++i)
+            if (lane == i) { my_r = pr[i]; my_s = pc[i]; }
+        const int jl = wave * KW + (lane < KW ? lane : 0);
+        const int32_t tau = L.tau[(uint32_t)(t - tau_base) + (uint32_t)jl];
+        const auto fin = C.fin_load(my_r, my_s, my_r);
         int S[KW];
         {
             int part[KW];
-#pragma unroll
-            for (int i = 0; i < KW; ++i) part[i] = C.lane_part(pr[i], pc[i]);
+            C.template lane_parts<KW>(pr, pc, pr, part);
             if constexpr (KW == 1) {
                 S[0] = wave_sum(part[0]);
             } else if constexpr (KW == 2) {
@@ -802,22 +875,19 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
                 S[3] = __builtin_amdgcn_readlane(z, 63);
             }
         }
-        // lane i < KW finishes proposal i of this wave
-        int my_r = pr[0], my_s = pc[0], my_S = S[0];
+        int my_S = S[0];
 #pragma unroll
         for (int i = 1; i < KW; ++i)
-            if (lane == i) { my_r = pr[i]; my_s = pc[i]; my_S = S[i]; }
-        const int dl = C.finish_pair(my_S, my_r, my_s);
-        const int jl = wave * KW + (lane < KW ? lane : 0);
+            if (lane == i) my_S = S[i];
+        const int dl = C.fin_eval(my_S, fin);
         const bool valid = lane < KW && (uint32_t)jl < rem;
-        const int32_t tau = L.tau[(uint32_t)(t - tau_base) + (uint32_t)jl];
         bool acc = valid && dl <= tau;
         bool tie = false;
         double zt = 0.0;
         if (valid && dl > 0 && (ring_exact || (dl >= tau - 1 && dl <= tau + 2)) &&
             !(t0_inf && inf_draw_clear(seed, chain_id, t + jl))) {
-            const bool ex = exact_test(dl, temps, T0, seed, chain_id, t + jl, &zt);
-            if (ring_exact) acc = ex;
+            zt = exact_z(dl, temps, T0, seed, chain_id, t + jl);
+            if (ring_exact) acc = zt < 0.0;
             tie = fabs(zt) < kNearTie;
         }
         const unsigned long long mask = __ballot(acc);
@@ -872,29 +942,34 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         constexpr int K = kWaves;
         if (tau_base == ~0ull || t + K + 1 > tau_base + ring_len) refill();
         const int r = r0, sn = uni(s0 + wave), sa = uni(s0 + 1 + wave);
+        // lane 0: the window's proposal at t + w; lane 1: the one after the
+        // swap, at t + 1 + w.  Their entries of A and B' and thresholds are
+        // read first, the dot products after them.
+        const bool after = lane == 1;
+        const uint32_t jo = (uint32_t)wave + (after ? 1u : 0u);
+        const int32_t tau = L.tau[(uint32_t)(t - tau_base) + jo];
+        const auto fin = C.fin_load(r, after ? sa : sn, after ? s0 : r);
         int Sn, Sa;
         {
-            const int pn = C.lane_part(r, sn), pa = C.lane_part(r, sa, s0);
-            const int z = row_sums(half_fold(pn, pa));
+            const int rr[2] = {r, r}, ss[2] = {sn, sa}, bb[2] = {r, s0};
+            int pp[2];
+            C.template lane_parts<2>(rr, ss, bb, pp);
+            const int z = row_sums(half_fold(pp[0], pp[1]));
             Sn = __builtin_amdgcn_readlane(z, 15) + __builtin_amdgcn_readlane(z, 31);
             Sa = __builtin_amdgcn_readlane(z, 47) + __builtin_amdgcn_readlane(z, 63);
         }
-        // lane 0: the window's proposal at t + w; lane 1: the one after the swap, at t + 1 + w
-        const int dn = C.finish_pair(Sn, r, sn), da = C.finish_after(Sa, r, sa, s0);
-        const bool after = lane == 1;
-        const int dl = after ? da : dn;
-        const uint32_t jo = (uint32_t)wave + (after ? 1u : 0u);
+        const int dl = C.fin_eval(after ? Sa : Sn, fin);
         const bool valid = lane < 2;
-        const int32_t tau = L.tau[(uint32_t)(t - tau_base) + jo];
         bool acc = valid && dl <= tau;
         bool tie = false;
         double zt = 0.0;
         if (valid && dl > 0 && (ring_exact || (dl >= tau - 1 && dl <= tau + 2)) &&
             !(t0_inf && inf_draw_clear(seed, chain_id, t + jo))) {
-            const bool ex = exact_test(dl, temps, T0, seed, chain_id, t + jo, &zt);
-            if (ring_exact) acc = ex;
+            zt = exact_z(dl, temps, T0, seed, chain_id, t + jo);
+            if (ring_exact) acc = zt < 0.0;
             tie = fabs(zt) < kNearTie;
         }
+        const int dn = __builtin_amdgcn_readlane(dl, 0), da = __builtin_amdgcn_readlane(dl, 1);
         const unsigned long long mask = __ballot(acc);
         if (lane == 0) {
             s_wkey[buf][wave] = (mask & 1ull) ? (((unsigned long long)wave << 32) | (uint32_t)dn) : ~0ull;
@@ -978,8 +1053,8 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
                     if (!acc && t0_inf && inf_draw_clear(seed, chain_id, t + jv[k])) {
                         acc = true;   // T = +inf: accepted, and no near tie
                     } else if (!acc && d <= bound) {
-                        double z;
-                        acc = exact_test(d, temps, T0, seed, chain_id, t + jv[k], &z);
+                        const double z = exact_z(d, temps, T0, seed, chain_id, t + jv[k]);
+                        acc = z < 0.0;
                         tie |= fabs(z) < kNearTie;
                     }
                     if (acc) mine = ((unsigned long long)jv[k] << 32) | (uint32_t)d;
@@ -1002,8 +1077,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
                 if (j > limit) break;
                 const int32_t d = L.D[rnd ? random_pair_index(seed, chain_id, t + j, m) : idx];
                 if (d > 0 && d <= bound) {
-                    double z;
-                    exact_test(d, temps, T0, seed, chain_id, t + j, &z);
+                    const double z = exact_z(d, temps, T0, seed, chain_id, t + j);
                     if (fabs(z) < kNearTie) log_tie(t + j, d, z);
                 }
                 idx += nt_mod;
