@@ -424,31 +424,66 @@ struct Chain {
         return finish_delta<SYM>(Sc, f.arr, f.ars, f.asr, f.ass, f.byy, f.bys, f.bsy, f.bss);
     }
 
-    // This wave's share of the swap (u, v) applied to B' (and B'^T): rows u
-    // and v are exchanged (whole dwords, then the two entries in columns u, v
-    // of each), and columns u, v are exchanged in every other row.  Shares
-    // touch disjoint bytes.
-    __device__ void swap_part(int u, int v) const
+    // This wave's share of the swap (u, v) applied to B' (and B'^T).
+    __device__ __forceinline__ void swap_part(int u, int v) const
     {
+        const int x[2] = {u, v}, src[2] = {v, u};
+        permute_part<2>(x, src);
+    }
+
+    // This wave's share of B'new[i][j] = B'[pi(i)][pi(j)] for a permutation pi
+    // that moves only the NC indices x[c], with pi(x[c]) = src[c] (a swap, or
+    // the 3-cycle of two swaps (r a), (r b) made in one pass: pi = (r a)(r b)
+    // maps r -> b, b -> a, a -> r).  Rows x[c] take rows src[c] (whole
+    // dwords; then lanes c * NC + e write the NC * NC entries in columns x,
+    // read with the rows), and in every other row the entries in columns x
+    // are permuted.  Each share issues all of its reads before its first
+    // write (a wave's LDS accesses are ordered); shares touch disjoint bytes.
+    template <int NC>
+    __device__ __forceinline__ void permute_part(const int (&x)[NC], const int (&src)[NC]) const
+    {
+        static_assert(NC == 2 || NC == 3, "a swap or a 3-cycle");
+        // the indices as plain values, so that the per-lane picks below stay
+        // selects (picks from an array would put the array in memory)
+        const int x0 = uni(x[0]), x1 = uni(x[1]), s0 = uni(src[0]), s1 = uni(src[1]);
+        int x2 = 0, s2 = 0;
+        if constexpr (NC == 3) { x2 = uni(x[2]); s2 = uni(src[2]); }
+        auto pick = [](int c, int a0, int a1, int a2) __attribute__((always_inline)) {
+            return c == 0 ? a0 : (c == 1 ? a1 : a2);
+        };
         auto rows = [&](uint8_t* M) __attribute__((always_inline)) {
-            uint32_t* mu = (uint32_t*)(M + u * P);
-            uint32_t* mv = (uint32_t*)(M + v * P);
+            const int l = lane < NC * NC ? lane : 0;   // lane l: corner entry (l / NC, l % NC)
+            const int ci = l / NC, ce = l - ci * NC;
+            const uint8_t corner = M[pick(ci, s0, s1, s2) * P + pick(ce, s0, s1, s2)];
             for (int k = lane; k < q; k += 64) {
-                const uint32_t x = mu[k], y = mv[k];
-                mu[k] = y;
-                mv[k] = x;
+                uint32_t w[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) w[c] = row(M, src[c])[k];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) ((uint32_t*)(M + x[c] * P))[k] = w[c];
             }
-            if (lane == 0) {   // after the row exchange (a wave's LDS accesses are ordered)
-                uint8_t x = M[u * P + u]; M[u * P + u] = M[u * P + v]; M[u * P + v] = x;
-                x = M[v * P + u]; M[v * P + u] = M[v * P + v]; M[v * P + v] = x;
-            }
+            if (lane < NC * NC) M[pick(ci, x0, x1, x2) * P + pick(ce, x0, x1, x2)] = corner;
         };
         auto cols = [&](uint8_t* M, int i0, int step) __attribute__((always_inline)) {
-            for (int i = i0; i < n; i += step) {
-                if (i == u || i == v) continue;
-                const uint8_t x = M[i * P + u];
-                M[i * P + u] = M[i * P + v];
-                M[i * P + v] = x;
+            for (int i = i0; i < n; i += 4 * step) {
+                uint8_t e[4][NC];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int ii = min(i + j * step, n - 1);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) e[j][c] = M[ii * P + src[c]];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int ii = i + j * step;
+                    bool own = ii < n;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) own = own && ii != x[c];
+                    if (own) {
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) M[ii * P + x[c]] = e[j][c];
+                    }
+                }
             }
         };
         if constexpr (SYM) {
@@ -619,8 +654,9 @@ struct Chain {
 template <int V> struct IC { static constexpr int value = V; };
 
 // TABU: tabu search over the same Delta instead of annealing (every iteration
-// takes the best admissible swap; rules at the tabu loop below).
-template <bool SYM, int PL, bool TABU = false>
+// takes the best admissible swap; rules at the tabu loop below).  PROF = false
+// compiles the phase counters out (for launches without them).
+template <bool SYM, int PL, bool TABU = false, bool PROF = true>
 __device__ void chain_run(const ChainArgs& a_in, char* smem)
 {
     // The chain's hot scalars live in scalar registers of every wave (all
@@ -628,8 +664,10 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
     // updates).  Scalar registers are scarce (102), so cold arguments are read
     // from an LDS copy where they are used and the running statistics are
     // kept by thread 0 alone.
-    __shared__ unsigned long long s_wkey[2][kWaves];   // per-wave first acceptance (j << 32 | Delta), by round parity
-    __shared__ unsigned long long s_akey[2][kWaves];   // the same for the proposals after the window's first (see scratch_round_ahead)
+    // per-wave first acceptance (j << 32 | Delta), by round parity; entries
+    // kWaves.. hold the same for the proposals after the window's first (see
+    // scratch_round_ahead), so that one read pass takes both
+    __shared__ unsigned long long s_wkey[2][2 * kWaves];
     __shared__ unsigned long long s_ties;
     __shared__ int s_flag;
     __shared__ unsigned long long s_prof[QAP_PHASES];
@@ -645,7 +683,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
     const uint32_t m = C.m;
 
     // phase counters: thread 0 adds to LDS without waiting for the result
-    const bool prof = a.prof != nullptr;
+    const bool prof = PROF && a.prof != nullptr;
     if (tid < QAP_PHASES) s_prof[tid] = 0;
     unsigned long long prof_last = prof ? clock64() : 0;
     const unsigned long long prof_start = prof_last;
@@ -731,7 +769,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
     int kw = 1;                              // proposals per wave in a scratch round
     uint64_t tau_base = ~0ull;               // the threshold ring covers [tau_base, tau_base + kRing)
     bool ring_exact = false;
-    uint32_t win_iters = 0, win_acc = 0;
+    uint32_t win = 0;   // the switch window: iterations (low 16 bits) and accepted swaps (high 16)
 
     // hash the buffered accept records (wave 0); the 64-bit sum over lanes is
     // taken in three 22-bit slices so that no slice can carry out
@@ -750,8 +788,9 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         nrec = 0;
     };
 
-    // the swap (u, v) at iteration tt with cost change d: scalars, p, B'
-    auto accept_common = [&](uint64_t tt, int u, int v, int d) __attribute__((always_inline)) {
+    // the swap (u, v) at iteration tt with cost change d: scalars, p, the
+    // record (B' is the caller's)
+    auto book = [&](uint64_t tt, int u, int v, int d) __attribute__((always_inline)) {
         if (tid == 0) {
             const int16_t pu = L.ps[u], pv = L.ps[v];
             L.ps[u] = pv; L.ps[v] = pu;
@@ -766,6 +805,10 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
             if (cost < best) { best = cost; best_iter = tt + 1; }
         }
         nrec += 1;
+    };
+    // ... and B'
+    auto accept_common = [&](uint64_t tt, int u, int v, int d) __attribute__((always_inline)) {
+        book(tt, u, v, d);
         C.swap_part(u, v);
     };
 
@@ -905,7 +948,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         if (tie && (jstar < 0 || jl <= jstar)) log_tie(t + jl, dl, zt);   // near ties a sequential run meets
         if (jstar < 0) {
             advance(rem);
-            win_iters += rem;
+            win += rem;
         } else {
             int u = r0, v = s0;
             if (rnd) {
@@ -921,8 +964,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
             __syncthreads();
             if (nrec == kRec) flush();
             advance((uint32_t)jstar + 1);
-            win_iters += (uint32_t)jstar + 1;
-            win_acc += 1;
+            win += (uint32_t)jstar + 1 + (1u << 16);
             mark(QAP_PH_SCRATCH_ACCEPT);
             bump(QAP_PH_N_SCRATCH_ACC, 1);
         }
@@ -973,17 +1015,21 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         const unsigned long long mask = __ballot(acc);
         if (lane == 0) {
             s_wkey[buf][wave] = (mask & 1ull) ? (((unsigned long long)wave << 32) | (uint32_t)dn) : ~0ull;
-            s_akey[buf][wave] = (mask & 2ull) ? (((unsigned long long)wave << 32) | (uint32_t)da) : ~0ull;
+            s_wkey[buf][kWaves + wave] = (mask & 2ull) ? (((unsigned long long)wave << 32) | (uint32_t)da) : ~0ull;
         }
         __syncthreads();
-        unsigned long long akey = s_akey[buf][0];
+        unsigned long long kv[2 * kWaves];
+#pragma unroll
+        for (int w = 0; w < 2 * kWaves; ++w) kv[w] = s_wkey[buf][w];
+        buf ^= 1;   // the other set is written next; everyone read this one before the next barrier
+        unsigned long long key = kv[0], akey = kv[kWaves];
 #pragma unroll
         for (int w = 1; w < kWaves; ++w) {
-            const unsigned long long x = s_akey[buf][w];
-            akey = x < akey ? x : akey;
+            key = kv[w] < key ? kv[w] : key;
+            akey = kv[kWaves + w] < akey ? kv[kWaves + w] : akey;
         }
+        key = uni64(key);
         akey = uni64(akey);
-        const unsigned long long key = min_key();   // flips buf
         const int jstar = key == ~0ull ? -1 : (int)(key >> 32);
         const int istar = (jstar != 0 || akey == ~0ull) ? -1 : (int)(akey >> 32);
         mark(QAP_PH_SCRATCH_EVAL);
@@ -994,28 +1040,33 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         if (tie && after && jstar == 0 && (istar < 0 || wave <= istar)) log_tie(t + jo, dl, zt);
         if (jstar < 0) {
             advance(K);
-            win_iters += K;
+            win += K;
             return;
         }
-        accept_common(t + jstar, r, s0 + jstar, (int)(uint32_t)key);
-        __syncthreads();
-        if (nrec == kRec) flush();
-        uint32_t used = (uint32_t)jstar + 1;
-        win_acc += 1;
-        if (jstar == 0) {
-            if (istar >= 0) {
-                accept_common(t + 1 + istar, r, s0 + 1 + istar, (int)(uint32_t)akey);
-                __syncthreads();
-                if (nrec == kRec) flush();
-                used = (uint32_t)istar + 2;
-                win_acc += 1;
-                bump(QAP_PH_N_SCRATCH_ACC, 1);
-            } else {
-                used = K + 1;   // the four proposals after the swap were all rejected
-            }
+        uint32_t used;
+        if (jstar == 0 && istar >= 0) {
+            // both swaps (r, s0) and (r, b): one pass permutes B' by their product
+            const int b = s0 + 1 + istar;
+            book(t, r, s0, (int)(uint32_t)key);
+            if (nrec == kRec) flush();
+            book(t + 1 + istar, r, b, (int)(uint32_t)akey);
+            const int x[3] = {r, s0, b}, src[3] = {b, r, s0};
+            C.template permute_part<3>(x, src);
+            __syncthreads();
+            if (nrec == kRec) flush();
+            used = (uint32_t)istar + 2;
+            win += 2u << 16;
+            bump(QAP_PH_N_SCRATCH_ACC, 1);
+        } else {
+            accept_common(t + jstar, r, s0 + jstar, (int)(uint32_t)key);
+            __syncthreads();
+            if (nrec == kRec) flush();
+            // after a first acceptance at j = 0, the four proposals after the swap were all rejected
+            used = jstar == 0 ? (uint32_t)K + 1 : (uint32_t)jstar + 1;
+            win += 1u << 16;
         }
         advance(used);
-        win_iters += used;
+        win += used;
         mark(QAP_PH_SCRATCH_ACCEPT);
         bump(QAP_PH_N_SCRATCH_ACC, 1);
     };
@@ -1205,7 +1256,8 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
             } else {
                 scratch_round(IC<4>{});
             }
-            if (win_iters >= kSwitchWindow) {
+            if ((win & 0xffffu) >= kSwitchWindow) {
+                const uint32_t win_iters = win & 0xffffu, win_acc = win >> 16;
                 // few proposals per round while most are accepted, more as acceptance
                 // falls: 1 per wave above 1/4, 2 above 1/8, else 4 (the cut points
                 // measured fastest for the N = 150 chain among 1/2..1/8 and 1/6..1/32)
@@ -1218,7 +1270,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
                     mark(QAP_PH_BUILD);
                     bump(QAP_PH_SWITCH_T, t);
                 }
-                win_iters = win_acc = 0;
+                win = 0;
             }
         } else {
             delta_step();
@@ -1261,11 +1313,11 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
     }
 }
 
-template <bool SYM, int PL>
+template <bool SYM, int PL, bool PROF>
 __global__ void __launch_bounds__(kThreads) k_chain_wg(ChainArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    chain_run<SYM, PL>(a, smem);
+    chain_run<SYM, PL, false, PROF>(a, smem);
 }
 
 template <bool SYM, int PL>
@@ -1433,17 +1485,22 @@ int launch_chain_wg(const ChainArgs& a, bool symmetric, int place, hipStream_t s
 {
     if (place < 0 || place >= kPlacements || (place >= 2 && a.gscratch == nullptr)) return QAP_E_INVAL;
     const size_t bytes = lds_wg_bytes(a.n, symmetric, place);
-    const void* fns[2][kPlacements] = {
-        {(const void*)k_chain_wg<false, 0>, (const void*)k_chain_wg<false, 1>, (const void*)k_chain_wg<false, 2>,
-         (const void*)k_chain_wg<false, 3>},
-        {(const void*)k_chain_wg<true, 0>, (const void*)k_chain_wg<true, 1>, (const void*)k_chain_wg<true, 2>,
-         (const void*)k_chain_wg<true, 3>}};
+    // with and without the phase counters
+    const void* fns[2][2][kPlacements] = {
+        {{(const void*)k_chain_wg<false, 0, false>, (const void*)k_chain_wg<false, 1, false>,
+          (const void*)k_chain_wg<false, 2, false>, (const void*)k_chain_wg<false, 3, false>},
+         {(const void*)k_chain_wg<true, 0, false>, (const void*)k_chain_wg<true, 1, false>,
+          (const void*)k_chain_wg<true, 2, false>, (const void*)k_chain_wg<true, 3, false>}},
+        {{(const void*)k_chain_wg<false, 0, true>, (const void*)k_chain_wg<false, 1, true>,
+          (const void*)k_chain_wg<false, 2, true>, (const void*)k_chain_wg<false, 3, true>},
+         {(const void*)k_chain_wg<true, 0, true>, (const void*)k_chain_wg<true, 1, true>,
+          (const void*)k_chain_wg<true, 2, true>, (const void*)k_chain_wg<true, 3, true>}}};
     const void* tfns[2][kPlacements] = {
         {(const void*)k_tabu_wg<false, 0>, (const void*)k_tabu_wg<false, 1>, (const void*)k_tabu_wg<false, 2>,
          (const void*)k_tabu_wg<false, 3>},
         {(const void*)k_tabu_wg<true, 0>, (const void*)k_tabu_wg<true, 1>, (const void*)k_tabu_wg<true, 2>,
          (const void*)k_tabu_wg<true, 3>}};
-    const void* fn = (tabu ? tfns : fns)[symmetric ? 1 : 0][place];
+    const void* fn = tabu ? tfns[symmetric ? 1 : 0][place] : fns[a.prof ? 1 : 0][symmetric ? 1 : 0][place];
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
         return QAP_E_DEVICE;
     ChainArgs args = a;
