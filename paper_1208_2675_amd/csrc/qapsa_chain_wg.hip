@@ -266,6 +266,14 @@ __device__ __noinline__ double exact_z(int d, const double* temps, double T0, ui
     return z;
 }
 
+// inf_draw_clear out of line: it is evaluated only when T0 = +inf, and an
+// inlined copy of the generator keeps its constants and key schedule in
+// registers for the whole run.
+__device__ __noinline__ bool inf_clear(uint64_t seed, uint32_t chain, uint64_t t)
+{
+    return inf_draw_clear(seed, chain, t);
+}
+
 // Acceptance threshold of iteration t: the largest Delta that Eq. (2) accepts
 // (Eq. (2) is monotone in Delta), in .x; .y is set when T_t is so large that
 // near ties cannot be located from the threshold alone.
@@ -928,7 +936,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         bool tie = false;
         double zt = 0.0;
         if (valid && dl > 0 && (ring_exact || (dl >= tau - 1 && dl <= tau + 2)) &&
-            !(t0_inf && inf_draw_clear(seed, chain_id, t + jl))) {
+            !(t0_inf && inf_clear(seed, chain_id, t + jl))) {
             zt = exact_z(dl, temps, T0, seed, chain_id, t + jl);
             if (ring_exact) acc = zt < 0.0;
             tie = fabs(zt) < kNearTie;
@@ -945,7 +953,9 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         const int jstar = key == ~0ull ? -1 : (int)(key >> 32);
         mark(QAP_PH_SCRATCH_EVAL);
         bump(QAP_PH_N_ROUNDS, 1);
-        if (tie && (jstar < 0 || jl <= jstar)) log_tie(t + jl, dl, zt);   // near ties a sequential run meets
+        if (__ballot(tie)) {   // rare: log the near ties a sequential run meets
+            if (tie && (jstar < 0 || jl <= jstar)) log_tie(t + jl, dl, zt);
+        }
         if (jstar < 0) {
             advance(rem);
             win += rem;
@@ -1006,7 +1016,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         bool tie = false;
         double zt = 0.0;
         if (valid && dl > 0 && (ring_exact || (dl >= tau - 1 && dl <= tau + 2)) &&
-            !(t0_inf && inf_draw_clear(seed, chain_id, t + jo))) {
+            !(t0_inf && inf_clear(seed, chain_id, t + jo))) {
             zt = exact_z(dl, temps, T0, seed, chain_id, t + jo);
             if (ring_exact) acc = zt < 0.0;
             tie = fabs(zt) < kNearTie;
@@ -1036,8 +1046,10 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
         bump(QAP_PH_N_ROUNDS, 1);
         // near ties a sequential run meets: the window's proposals up to the
         // first acceptance, and those after the swap when it is the first one
-        if (tie && !after && (jstar < 0 || wave <= jstar)) log_tie(t + jo, dl, zt);
-        if (tie && after && jstar == 0 && (istar < 0 || wave <= istar)) log_tie(t + jo, dl, zt);
+        if (__ballot(tie)) {   // rare
+            if (tie && !after && (jstar < 0 || wave <= jstar)) log_tie(t + jo, dl, zt);
+            if (tie && after && jstar == 0 && (istar < 0 || wave <= istar)) log_tie(t + jo, dl, zt);
+        }
         if (jstar < 0) {
             advance(K);
             win += K;
@@ -1101,7 +1113,7 @@ __device__ void chain_run(const ChainArgs& a_in, char* smem)
                     const int32_t d = dv[k];
                     if (mine != ~0ull || d == INT_MAX) continue;
                     bool acc = d <= 0;
-                    if (!acc && t0_inf && inf_draw_clear(seed, chain_id, t + jv[k])) {
+                    if (!acc && t0_inf && inf_clear(seed, chain_id, t + jv[k])) {
                         acc = true;   // T = +inf: accepted, and no near tie
                     } else if (!acc && d <= bound) {
                         const double z = exact_z(d, temps, T0, seed, chain_id, t + jv[k]);
