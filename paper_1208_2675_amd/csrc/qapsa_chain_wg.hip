@@ -1343,8 +1343,8 @@ __global__ void __launch_bounds__(kThreads) k_tabu_wg(ChainArgs a)
 // next chain from a device-wide queue and runs it (or its next slice) with the
 // one-workgroup routine above.  One instantiation per placement; each skips
 // the chains of the other placements, so all can walk the same descriptor
-// array concurrently.
-template <int PL>
+// array concurrently.  PROF as for k_chain_wg.
+template <int PL, bool PROF>
 __global__ void __launch_bounds__(kThreads) k_chain_batch(BatchArgs b)
 {
     extern __shared__ __align__(16) char smem[];
@@ -1381,8 +1381,8 @@ __global__ void __launch_bounds__(kThreads) k_chain_batch(BatchArgs b)
         a.seed = d.seed;
         a.chain_id = d.chain_id;
         a.gscratch = d.scratch;
-        if (d.symmetric) chain_run<true, PL>(a, smem);
-        else chain_run<false, PL>(a, smem);
+        if (d.symmetric) chain_run<true, PL, false, PROF>(a, smem);
+        else chain_run<false, PL, false, PROF>(a, smem);
         __syncthreads();
     }
 }
@@ -1416,8 +1416,12 @@ int launch_chain_batch(const BatchArgs& b, int groups, const int count[4], int t
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return QAP_E_DEVICE;
-    const void* fns[kPlacements] = {(const void*)k_chain_batch<0>, (const void*)k_chain_batch<1>,
-                                    (const void*)k_chain_batch<2>, (const void*)k_chain_batch<3>};
+    const void* const fns_all[2][kPlacements] = {
+        {(const void*)k_chain_batch<0, false>, (const void*)k_chain_batch<1, false>,
+         (const void*)k_chain_batch<2, false>, (const void*)k_chain_batch<3, false>},
+        {(const void*)k_chain_batch<0, true>, (const void*)k_chain_batch<1, true>,
+         (const void*)k_chain_batch<2, true>, (const void*)k_chain_batch<3, true>}};
+    const void* const* fns = fns_all[b.prof ? 1 : 0];
     int g[kPlacements] = {0, 0, 0, 0};
     double full[kPlacements] = {0, 0, 0, 0};   // workgroups of the placement that fill the GPU
     int kinds = 0;
