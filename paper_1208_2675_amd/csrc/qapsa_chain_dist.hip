@@ -1204,8 +1204,8 @@ __global__ void __launch_bounds__(512) k_chain_dist(DistArgs a)
                     ar[h] = __builtin_bit_cast(v2i16, labp[r]);
                     br[h] = __builtin_bit_cast(v2i16, lbbp[r]);
                 }
-                // two of this thread's columns at a time
-                constexpr int kCols = 2;
+                // four of this thread's columns at a time (all of them at n <= 4 * threads)
+                constexpr int kCols = 4;
                 for (int i0 = 0; i0 < nk; i0 += kCols) {
                     v2i16 as[kCols], bs[kCols];
                     int32_t dv[kCols][kRowBatch];
