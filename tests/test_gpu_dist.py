@@ -264,3 +264,27 @@ def test_dispatch_choices_do_not_change_the_run(orc, Q, sym, flags, window):
         assert got[k] == ref[k], (k, got[k], ref[k])
     assert np.array_equal(got["p"], ref["p"])
     assert np.array_equal(got["delta"], orc.delta_matrix(A, B, got["p"]))
+
+
+@pytest.mark.parametrize("n,sym", [(300, False), (420, True), (257, False)])
+def test_single_workgroup_beyond_one_pass_matches_oracle(orc, Q, n, sym):
+    """The one-workgroup kernel forced (QAP_FLAG_SINGLE_WG) past n = 256, where
+    a scratch round's dot products take more than one k per lane and a swap's
+    column share more than one pass of four rows per lane (matrices in device
+    memory, placements 2-3): its whole schedule, look-ahead rounds and double
+    swaps included, equals the oracle's run."""
+    A, B, p0 = _sym(n, 31 + n) if sym else _asym(n, 32 + n)
+    iters = 30000
+    s = orc.schedule(A, B, p0, iters)
+    T0 = 20 * s["T0"]   # a hot start: about 40% of the run accepted, in scratch mode
+    ref = orc.sa_run(A, B, p0, iters, T0, s["alpha"], 12, 0, tie_cap=16)
+    print(f"[case] single-wg n={n} sym={sym} iters={iters}", flush=True)
+    c = Q.Chain(A, B, p0, iters, 12, 0, T0=T0, flags=Q.QAP_FLAG_SINGLE_WG).init()
+    c.run(9000)
+    c.run()
+    got = c.result(with_delta=True)
+    for k in ("t", "accepts", "hash", "cost", "best_cost", "best_iter", "near_ties"):
+        assert got[k] == ref[k], (k, got[k], ref[k])
+    assert np.array_equal(got["p"], ref["p"])
+    assert np.array_equal(got["delta"], orc.delta_matrix(A, B, got["p"]))
+    assert ref["accepts"] > iters // 3   # much of the run at high acceptance
