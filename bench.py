@@ -95,8 +95,8 @@ def log(msg):
 
 
 def cpu_threads() -> int:
-    """Host threads for the all-core CPU baselines: the machine's CPU share for one
-    GPU (16), less one for the thread that drives the GPU."""
+    """Host threads for the all-core CPU baselines: the host's CPU share for one
+    GPU (16 threads), less one for the thread that drives the GPU."""
     return max(1, min(16, os.cpu_count() or 1) - 1)
 
 
