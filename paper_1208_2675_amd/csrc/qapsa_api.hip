@@ -398,8 +398,13 @@ QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return QAP_E_DEVICE;
     const int min_place = n_chains > cus ? 1 : 0;
-    size_t lds[4] = {0, 0, 0, 0};
-    int kinds[4] = {0, 0, 0, 0};
+    // With more chains than CUs, the chains whose LDS fits twice in a CU run
+    // in launches of their own (class 0), sized by their own largest chain,
+    // so that two of them share a CU instead of each taking a CU's LDS as
+    // the largest chains of the placement do (class 1).
+    uint32_t lds_split = n_chains > cus ? (uint32_t)(kLdsLimit / 2 - kLdsStaticReserve) : 0u;
+    size_t lds[kBatchKinds] = {}, lds1[kBatchKinds] = {};   // with the split, and with one class
+    int kinds[kBatchKinds] = {}, kinds1[kBatchKinds] = {};
     for (int i = 0; i < n_chains; ++i) {
         const qap_chain_desc& d = host_descs[i];
         if (d.n < 2 || d.n > 46340 || !d.A || !d.Bp || !d.p || !d.delta || !d.state || !d.temps) return QAP_E_INVAL;
@@ -413,8 +418,19 @@ QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,
         if (place < min_place) place = min_place;
         if (place >= 2 && !d.scratch) return QAP_E_INVAL;
         const size_t b = lds_wg_bytes(d.n, d.symmetric != 0, place);
-        if (b > lds[place]) lds[place] = b;
-        kinds[place] += 1;
+        const int kind = 2 * place + (lds_split && b > lds_split ? 1 : 0);
+        if (b > lds[kind]) lds[kind] = b;
+        kinds[kind] += 1;
+        if (b > lds1[2 * place]) lds1[2 * place] = b;
+        kinds1[2 * place] += 1;
+    }
+    // at most four kernels side by side (the caller's stream and three side
+    // streams): else one class per placement
+    int nonempty = 0;
+    for (int k = 0; k < kBatchKinds; ++k) nonempty += kinds[k] > 0;
+    if (nonempty > 4) {
+        lds_split = 0;
+        for (int k = 0; k < kBatchKinds; ++k) { lds[k] = lds1[k]; kinds[k] = kinds1[k]; }
     }
     BatchArgs b{};
     b.n_chains = n_chains;
@@ -424,6 +440,7 @@ QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,
     b.ws = (BatchWs*)workspace;
     b.slice = cfg->slice;
     b.prof = cfg->phase_cycles;
+    b.lds_split = lds_split;
     return launch_chain_batch(b, cfg->groups, kinds, threads, lds, stream);
 }
 

@@ -1343,13 +1343,15 @@ __global__ void __launch_bounds__(kThreads) k_tabu_wg(ChainArgs a)
 // next chain from a device-wide queue and runs it (or its next slice) with the
 // one-workgroup routine above.  One instantiation per placement; each skips
 // the chains of the other placements, so all can walk the same descriptor
-// array concurrently.  PROF as for k_chain_wg.
+// array concurrently.  With an LDS split, a launch of the same placement runs
+// either the chains whose LDS bytes exceed it (cls 1) or the others (cls 0),
+// each kind with its own queue position.  PROF as for k_chain_wg.
 template <int PL, bool PROF>
 __global__ void __launch_bounds__(kThreads) k_chain_batch(BatchArgs b)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_idx;
-    unsigned* next = &b.ws->next[PL];
+    unsigned* next = &b.ws->next[2 * PL + b.cls];
     for (;;) {
         if (threadIdx.x == 0) s_idx = (int)atomicAdd(next, 1u);
         __syncthreads();
@@ -1361,6 +1363,9 @@ __global__ void __launch_bounds__(kThreads) k_chain_batch(BatchArgs b)
         int pc = wg_placement(d.n, d.symmetric != 0);
         if (pc < b.min_place) pc = b.min_place;
         if (pc != PL) continue;
+        if (b.lds_split && (wg_layout(d.n, wg_quads_of(d.n), d.symmetric != 0, pc, nullptr, nullptr) > b.lds_split) !=
+                               (b.cls != 0))
+            continue;
         ChainArgs a{};
         a.n = d.n;
         a.quads = wg_quads_of(d.n);
@@ -1389,7 +1394,7 @@ __global__ void __launch_bounds__(kThreads) k_chain_batch(BatchArgs b)
 
 __global__ void k_batch_reset(BatchWs* ws)
 {
-    for (int i = 0; i < kPlacements; ++i) ws->next[i] = 0;
+    for (int i = 0; i < kBatchKinds; ++i) ws->next[i] = 0;
 }
 
 }  // namespace
@@ -1408,8 +1413,8 @@ size_t wg_scratch_bytes(int n, bool symmetric, int place)
     return wg_global_bytes(n, wg_quads_of(n), symmetric, place);
 }
 
-int launch_chain_batch(const BatchArgs& b, int groups, const int count[4], int threads, const size_t lds[4],
-                       hipStream_t stream)
+int launch_chain_batch(const BatchArgs& b, int groups, const int count[kBatchKinds], int threads,
+                       const size_t lds[kBatchKinds], hipStream_t stream)
 {
     if (threads != kThreads) return QAP_E_INVAL;
     int dev = 0, cus = 0;
@@ -1422,55 +1427,54 @@ int launch_chain_batch(const BatchArgs& b, int groups, const int count[4], int t
         {(const void*)k_chain_batch<0, true>, (const void*)k_chain_batch<1, true>,
          (const void*)k_chain_batch<2, true>, (const void*)k_chain_batch<3, true>}};
     const void* const* fns = fns_all[b.prof ? 1 : 0];
-    int g[kPlacements] = {0, 0, 0, 0};
-    double full[kPlacements] = {0, 0, 0, 0};   // workgroups of the placement that fill the GPU
+    int g[kBatchKinds] = {};
+    double full[kBatchKinds] = {};   // workgroups of the kind that fill the GPU
     int kinds = 0;
-    for (int pl = 0; pl < kPlacements; ++pl) {
-        if (count[pl] == 0) continue;
+    for (int k = 0; k < kBatchKinds; ++k) {
+        if (count[k] == 0) continue;
         kinds += 1;
-        if (hipFuncSetAttribute(fns[pl], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds[pl]) != hipSuccess)
+        const void* fn = fns[k / 2];
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds[k]) != hipSuccess)
             return QAP_E_DEVICE;
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fns[pl], kThreads, lds[pl]) != hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds[k]) != hipSuccess)
             return QAP_E_DEVICE;
-        full[pl] = (double)(per_cu < 1 ? 1 : per_cu) * cus;
-        const int gg = groups > 0 ? groups : (int)full[pl];
-        g[pl] = gg > count[pl] ? count[pl] : gg;
+        full[k] = (double)(per_cu < 1 ? 1 : per_cu) * cus;
+        const int gg = groups > 0 ? groups : (int)full[k];
+        g[k] = gg > count[k] ? count[k] : gg;
     }
+    if (kinds > 4) return QAP_E_INVAL;   // the caller's stream and three side streams
     // The kernels run side by side, and the hardware may dispatch them in any
     // order.  So that none of them waits for another's workgroups to finish,
     // all of them must be resident at once: when their shares of the GPU add
-    // up to more than one, the placements of the smaller chains get fewer
+    // up to more than one, the kinds of the smaller chains get fewer
     // (persistent) workgroups, each then running more chains in turn.
     if (groups <= 0 && kinds > 1) {
         double used = 0;
-        for (int pl = kPlacements - 1; pl >= 0; --pl) {
-            if (g[pl] == 0) continue;
+        for (int k = kBatchKinds - 1; k >= 0; --k) {
+            if (g[k] == 0) continue;
             const double left = 1.0 - used;
-            const int fit = (int)(left * full[pl]);
-            if (g[pl] > fit) g[pl] = fit < 1 ? 1 : fit;
-            used += g[pl] / full[pl];
+            const int fit = (int)(left * full[k]);
+            if (g[k] > fit) g[k] = fit < 1 ? 1 : fit;
+            used += g[k] / full[k];
         }
     }
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, stream, b.ws);
-    BatchArgs args = b;
-    void* kargs[] = {&args};
-    if (kinds <= 1) {
-        for (int pl = 0; pl < kPlacements; ++pl)
-            if (g[pl] > 0 && hipLaunchKernel(fns[pl], dim3(g[pl]), dim3(kThreads), kargs, lds[pl], stream) != hipSuccess)
-                return QAP_E_DEVICE;
-        return QAP_OK;
+    BatchArgs args[kBatchKinds];
+    for (int k = 0; k < kBatchKinds; ++k) {
+        args[k] = b;
+        args[k].cls = k % 2;
     }
     // the kinds run side by side: the first on the caller's stream, the others
-    // on side streams forked from it and joined back.  The placements of the
+    // on side streams forked from it and joined back.  The kinds of the
     // largest chains are launched first, so that their workgroups (the
     // longest-running ones) are dispatched before the small chains take the
     // CUs.
-    hipStream_t used[kPlacements];
-    hipEvent_t joins[kPlacements];
+    hipStream_t used[kBatchKinds];
+    hipEvent_t joins[kBatchKinds];
     int nused = 0;
-    for (int pl = kPlacements - 1; pl >= 0; --pl) {
-        if (g[pl] == 0) continue;
+    for (int k = kBatchKinds - 1; k >= 0; --k) {
+        if (g[k] == 0) continue;
         if (nused == 0) {
             used[nused++] = stream;
             continue;
@@ -1484,15 +1488,16 @@ int launch_chain_batch(const BatchArgs& b, int groups, const int count[4], int t
         joins[nused] = join;
         ++nused;
     }
-    int k = 0;
-    for (int pl = kPlacements - 1; pl >= 0; --pl) {
-        if (g[pl] == 0) continue;
-        if (hipLaunchKernel(fns[pl], dim3(g[pl]), dim3(kThreads), kargs, lds[pl], used[k]) != hipSuccess)
+    int i = 0;
+    for (int k = kBatchKinds - 1; k >= 0; --k) {
+        if (g[k] == 0) continue;
+        void* kargs[] = {&args[k]};
+        if (hipLaunchKernel(fns[k / 2], dim3(g[k]), dim3(kThreads), kargs, lds[k], used[i]) != hipSuccess)
             return QAP_E_DEVICE;
-        ++k;
+        ++i;
     }
-    for (int i = 1; i < nused; ++i)
-        if (hipEventRecord(joins[i], used[i]) != hipSuccess || hipStreamWaitEvent(stream, joins[i], 0) != hipSuccess)
+    for (int j = 1; j < nused; ++j)
+        if (hipEventRecord(joins[j], used[j]) != hipSuccess || hipStreamWaitEvent(stream, joins[j], 0) != hipSuccess)
             return QAP_E_DEVICE;
     return QAP_OK;
 }

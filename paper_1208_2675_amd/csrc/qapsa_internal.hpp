@@ -167,9 +167,13 @@ int dist_scratch_groups(int n, int G, bool symmetric, int esize, size_t budget);
 int launch_chain_dist(const DistArgs& a, bool symmetric, int esize, int G, int threads, hipStream_t stream);
 
 // batched chains (one persistent launch, a device-wide work queue)
+// Kinds of batched launch: placement x LDS class (class 1: the chains whose
+// LDS bytes exceed BatchArgs::lds_split, class 0: the others), kind = 2 *
+// placement + class.
+constexpr int kBatchKinds = 2 * 4;
 struct BatchWs {
-    unsigned next[4];   // queue positions of the kernels of placement 0 .. 3
-    unsigned pad[12];
+    unsigned next[kBatchKinds];   // queue positions of the kernels of each kind
+    unsigned pad[16 - kBatchKinds];
 };
 struct BatchArgs {
     int32_t n_chains;
@@ -179,10 +183,13 @@ struct BatchArgs {
     BatchWs* ws;
     uint64_t slice;
     uint64_t* prof;
+    uint32_t lds_split;           // LDS bytes that separate the two classes (0: one class)
+    int32_t cls;                  // the class this launch runs
 };
 // groups <= 0: as many workgroups as can be resident at once (occupancy of each
 // kernel at its LDS size times the CU count), never more than its chains
-int launch_chain_batch(const BatchArgs& b, int groups, const int count[4], int threads, const size_t lds[4],
+int launch_chain_batch(const BatchArgs& b, int groups, const int count[kBatchKinds], int threads,
+                       const size_t lds[kBatchKinds],
                        hipStream_t stream);
 // a second stream (default priority) and two events of the current device, created once
 int side_stream(int which, hipStream_t* side, hipEvent_t* fork, hipEvent_t* join);
