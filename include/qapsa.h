@@ -432,7 +432,8 @@ QAP_API uint64_t qap_batch_workspace_bytes(void);
  * see qap_single_workgroup); otherwise QAP_E_UNSUPPORTED.
  * With more chains than the device has CUs, chains that fit LDS entirely keep
  * Delta in their delta buffer instead (less LDS per workgroup, more chains at
- * once); results do not change.
+ * once), and the chains whose LDS fits twice in a CU run in launches of their
+ * own beside those of the larger chains; results do not change.
  * Chains in one batch must not share state, p, Bp or delta buffers.
  */
 QAP_API int qap_sa_run_batch(int32_t n_chains, const qap_chain_desc* host_descs,
