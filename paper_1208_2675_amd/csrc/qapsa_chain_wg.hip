@@ -1397,6 +1397,14 @@ __global__ void k_batch_reset(BatchWs* ws)
     for (int i = 0; i < kBatchKinds; ++i) ws->next[i] = 0;
 }
 
+// Holds its stream for `ticks` of the constant-rate wall clock, so that the
+// kernel queued behind it is dispatched after those of the other streams.
+__global__ void k_hold(uint64_t ticks)
+{
+    const uint64_t t0 = wall_clock64();
+    while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
+}
+
 }  // namespace
 
 int wg_quads(int n) { return wg_quads_of(n); }   // odd dword pitch: strided row reads hit distinct banks
@@ -1465,23 +1473,36 @@ int launch_chain_batch(const BatchArgs& b, int groups, const int count[kBatchKin
         args[k] = b;
         args[k].cls = k % 2;
     }
-    // the kinds run side by side: the first on the caller's stream, the others
-    // on side streams forked from it and joined back.  The kinds of the
-    // largest chains are launched first, so that their workgroups (the
-    // longest-running ones) are dispatched before the small chains take the
-    // CUs.
+    // With LDS classes and one kind of small chains (class 0), that kind runs
+    // last on the caller's stream, behind a short hold: the hardware may
+    // dispatch side-by-side kernels in any order, and class-0 workgroups
+    // dispatched first would take a little LDS on every CU and leave none
+    // whole for the larger chains, which would then wait for them (3.2 s
+    // instead of 2.5 s for the 512-chain mix).
+    int small = -1, nsmall = 0;
+    if (b.lds_split && kinds > 1)
+        for (int k = 0; k < kBatchKinds; k += 2)
+            if (g[k] > 0) { small = k; ++nsmall; }
+    if (nsmall != 1) small = -1;
+    // the other kinds run side by side: the first on the caller's stream
+    // (when no small kind takes it), the others on side streams forked from
+    // it and joined back.  The kinds of the largest chains are launched first,
+    // so that their workgroups (the longest-running ones) are dispatched
+    // before the small chains take the CUs.
     hipStream_t used[kBatchKinds];
     hipEvent_t joins[kBatchKinds];
     int nused = 0;
     for (int k = kBatchKinds - 1; k >= 0; --k) {
         if (g[k] == 0) continue;
-        if (nused == 0) {
+        if (nused == 0 && small < 0) {
             used[nused++] = stream;
             continue;
         }
+        if (k == small) continue;
+        const int which = small < 0 ? nused - 1 : nused;
         hipStream_t side;
         hipEvent_t fork, join;
-        if (side_stream(nused - 1, &side, &fork, &join) != QAP_OK) return QAP_E_DEVICE;
+        if (side_stream(which, &side, &fork, &join) != QAP_OK) return QAP_E_DEVICE;
         if (hipEventRecord(fork, stream) != hipSuccess || hipStreamWaitEvent(side, fork, 0) != hipSuccess)
             return QAP_E_DEVICE;
         used[nused] = side;
@@ -1490,13 +1511,21 @@ int launch_chain_batch(const BatchArgs& b, int groups, const int count[kBatchKin
     }
     int i = 0;
     for (int k = kBatchKinds - 1; k >= 0; --k) {
-        if (g[k] == 0) continue;
+        if (g[k] == 0 || k == small) continue;
         void* kargs[] = {&args[k]};
         if (hipLaunchKernel(fns[k / 2], dim3(g[k]), dim3(kThreads), kargs, lds[k], used[i]) != hipSuccess)
             return QAP_E_DEVICE;
         ++i;
     }
-    for (int j = 1; j < nused; ++j)
+    if (small >= 0) {
+        int khz = 0;   // the wall clock's rate
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+        hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, stream, (uint64_t)khz * 30 / 1000);   // 30 us
+        void* kargs[] = {&args[small]};
+        if (hipLaunchKernel(fns[small / 2], dim3(g[small]), dim3(kThreads), kargs, lds[small], stream) != hipSuccess)
+            return QAP_E_DEVICE;
+    }
+    for (int j = small < 0 ? 1 : 0; j < nused; ++j)
         if (hipEventRecord(joins[j], used[j]) != hipSuccess || hipStreamWaitEvent(stream, joins[j], 0) != hipSuccess)
             return QAP_E_DEVICE;
     return QAP_OK;
