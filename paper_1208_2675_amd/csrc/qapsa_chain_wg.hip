@@ -1474,7 +1474,7 @@ int launch_chain_batch(const BatchArgs& b, int groups, const int count[kBatchKin
         args[k].cls = k % 2;
     }
     // With LDS classes and one kind of small chains (class 0), that kind runs
-    // last on the caller's stream, behind a short hold: the hardware may
+    // last on the caller's stream, behind a 1 ms hold: the hardware may
     // dispatch side-by-side kernels in any order, and class-0 workgroups
     // dispatched first would take a little LDS on every CU and leave none
     // whole for the larger chains, which would then wait for them (3.2 s
@@ -1520,7 +1520,7 @@ int launch_chain_batch(const BatchArgs& b, int groups, const int count[kBatchKin
     if (small >= 0) {
         int khz = 0;   // the wall clock's rate
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
-        hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, stream, (uint64_t)khz * 30 / 1000);   // 30 us
+        hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, stream, (uint64_t)khz);   // 1 ms
         void* kargs[] = {&args[small]};
         if (hipLaunchKernel(fns[small / 2], dim3(g[small]), dim3(kThreads), kargs, lds[small], stream) != hipSuccess)
             return QAP_E_DEVICE;
